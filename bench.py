@@ -1,0 +1,180 @@
+#!/usr/bin/env python3
+"""Benchmark: full lower-triangular CSR construction of K (integrate + assemble) on one MI355X.
+
+Workload (default): 150^3 cubes split into 6 Kuhn tet4 each (20,250,000 elements,
+3,442,951 nodes), interior jitter 0.2h, random node and element numbering,
+c log-uniform in [1e-3, 1e3], FP32 integration with FP64 Jacobian fallback.
+A step is one complete construction from device-resident E, C, c to device-resident
+row_ptr / col_idx / vals.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c2|c1|c5] [--prec ...]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "elements/s for full lower-tri CSR K build (integrate+assemble), % HBM peak"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "c1": (1, "hex8 unit cube 10^3 (1,000 elements, 1,331 nodes), jitter 0.2h, c=1", "fp64"),
+    "c2": (2, "hex8 box 100^3 (1,000,000 elements, 1,030,301 nodes), jitter 0.25h, random node numbering, "
+              "c log-U[1e-2,1e2]", "fp32fb64"),
+    "c3": (3, "tet4 Kuhn 6x150^3 (20,250,000 elements, 3,442,951 nodes), jitter 0.2h, random node and element "
+              "numbering, c log-U[1e-3,1e3], 1-point rule", "fp32fb64"),
+    "c5": (5, "hex8 box 64^3 (262,144 elements), jitter 0.2h, c log-U[1e-1,1e1]", "fp64"),
+}
+
+
+def algorithmic_bytes(elem: int, n_elem: int, n_node: int, nnz: int, prec: str) -> dict:
+    """Compulsory HBM bytes of each stage and of the whole path (per launch).
+
+    Inputs read once, outputs written once; the per-element lower values (T_e values)
+    are written once and read once, and the row-ordered (col, value) list is written
+    once and read once; coordinates are counted once per node.
+    """
+    vb = 8 if prec == "fp64" else 4
+    nen = elem
+    te = nen * (nen + 1) // 2
+    T = n_elem * te
+    conn = 4 * nen * n_elem
+    coef = 8 * n_elem
+    coords = 24 * n_node
+    b = {
+        "count": conn + 4 * n_node,                              # E in, row counts out
+        "scan_rows": 8 * n_node,                                  # counts in, starts out
+        "integrate": conn + coef + coords + vb * T,               # E, c, C in; lower values out
+        "scatter": conn + vb * T + 4 * n_node + (4 + vb) * T,     # E, values, row starts in; (col, val) out
+        "reduce": 4 * n_node + (4 + vb) * T + (4 + vb) * nnz + 4 * n_node,
+        "compress": 8 * n_node + 2 * (4 + vb) * nnz + 4 * n_node,
+    }
+    # the path as a whole: E, c, C in once, lower values once out and in, CSR out
+    b["path"] = conn + coef + coords + 2 * vb * T + (4 + vb) * nnz + 4 * (n_node + 1)
+    return b
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
+    ap.add_argument("--prec", default=None, choices=["fp64", "fp32", "fp32fb64"])
+    ap.add_argument("--no-fp64", action="store_true", help="skip the all-FP64 comparison run")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-sample", type=int, default=10_000_000, help="elements in the oracle's timed sample")
+    ap.add_argument("--profile-steps", action="store_true", help="no stage events (for profiler runs)")
+    return ap.parse_args()
+
+
+def time_builds(kb, torch, mesh_dev, m, prec, steps, warmup, stage_events=True):
+    conn, coords, coef = mesh_dev
+    b = kb.Builder(m.elem, m.n_elem, m.n_node, prec=prec)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        b.run(conn, coords, coef)
+    res = b.result(check=True, allow_flags=0)
+    n_ev = kb.KB_N_STAGES + 1
+    evs = [kb._lib.HipEvents(n_ev) for _ in range(steps)] if stage_events else None
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    t0.record(stream)
+    for s in range(steps):
+        b.run(conn, coords, coef, stage_events=evs[s].handles if evs else None)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = t0.elapsed_time(t1) / steps
+    stages = None
+    if evs:
+        stages = {}
+        for i, name in enumerate(kb.STAGE_NAMES):
+            stages[name] = sum(evs[s].elapsed_ms(i, i + 1) for s in range(steps)) / steps
+        for e in evs:
+            e.close()
+    res = b.result(check=True, allow_flags=0)
+    return ms, wall / steps * 1e3, stages, res
+
+
+def cpu_baseline(m, sample):
+    import numpy as np
+
+    import meshgen
+    import oracle
+
+    n = min(sample, m.n_elem)
+    sub = meshgen.Mesh(m.elem, np.ascontiguousarray(m.conn[:n]), m.coords, np.ascontiguousarray(m.coef[:n]))
+    oracle.lib()
+    t = time.perf_counter()
+    oracle.build_mesh(sub)
+    dt = time.perf_counter() - t
+    return {"value": n / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n:,} of the {m.n_elem:,} elements (all {m.n_node:,} nodes), single-threaded FP64 "
+                      f"C oracle, integrate + sort + CSR, {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU design is described "
+              "in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import meshgen
+    import paper_1501_04784_amd as kb
+
+    cid, desc, default_prec = WORKLOADS[args.workload]
+    prec = args.prec or default_prec
+    print(f"[bench] generating workload {args.workload}: {desc}", file=sys.stderr, flush=True)
+    m = meshgen.config_mesh(cid)
+    dev = torch.device("cuda:0")
+    mesh_dev = (torch.from_numpy(m.conn).to(dev), torch.from_numpy(m.coords).to(dev), torch.from_numpy(m.coef).to(dev))
+    torch.cuda.synchronize()
+    print(f"[bench] {m.n_elem} elements, {m.n_node} nodes on device; timing {prec}", file=sys.stderr, flush=True)
+
+    ms, wall_ms, stages, res = time_builds(kb, torch, mesh_dev, m, prec, args.steps, args.warmup,
+                                           stage_events=not args.profile_steps)
+    nnz = res.nnz
+    print(f"[bench] {prec}: {ms:.3f} ms/step, nnz {nnz}, fallback elements {res.n_fallback}", file=sys.stderr,
+          flush=True)
+    value = m.n_elem / (ms * 1e-3)
+    ab = algorithmic_bytes(m.elem, m.n_elem, m.n_node, nnz, prec)
+    out = {
+        "metric": METRIC, "value": value, "unit": "elements/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == "fp64" else "f32", "data": "synthetic",
+        "config": {"workload": desc, "n_elem": m.n_elem, "n_node": m.n_node, "nnz": nnz, "precision": prec,
+                   "fp64_fallback_elements": res.n_fallback, "parallelism": "single GPU"},
+        "path_hbm_frac": ab["path"] / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
+    }
+    if stages:
+        dom = max((k for k in stages if k in ab), key=lambda k: stages[k])
+        achieved = ab[dom] / (stages[dom] * 1e-3) / 1e9
+        out["roofline"] = {"bound": "hbm", "kernel_stage": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None}
+        out["stages_ms"] = stages
+    if not args.no_fp64 and prec != "fp64":
+        ms64, _, st64, r64 = time_builds(kb, torch, mesh_dev, m, "fp64", max(3, args.steps // 2), 2,
+                                         stage_events=False)
+        out["fp64"] = {"ms_per_step": ms64, "value": m.n_elem / (ms64 * 1e-3)}
+        out["speedup_vs_fp64"] = ms64 / ms
+        print(f"[bench] fp64: {ms64:.3f} ms/step", file=sys.stderr, flush=True)
+    if not args.no_cpu:
+        print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(m, args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,169 @@
+/*
+ * kbuild.h -- C ABI of the MI355X (gfx950) builder of the lower-triangular global
+ * stiffness matrix K of the 3D Poisson equation div(c grad phi) = 0.
+ *
+ * What is computed (Ramirez-Gil, Tsuzuki, Montealegre-Rubio, "Global finite element
+ * matrix construction based on a CPU-GPU implementation"):
+ *   - Eq. 6:  K = sum_e k_e  (assembly as a sum of element matrices);
+ *   - Eq. 7-9: k_e = c_e * sum_q W_q |J_q| B_q^T B_q, where B = J^{-1} dN is the 3 x nen
+ *     matrix of physical shape-function gradients, J = dN X (J_ij = dx_j / dxi_i) and
+ *     c_e is constant per element (the paper's MP array, Section 2);
+ *   - Section 3 / Alg. 2: only the lower triangle of each symmetric k_e is computed,
+ *     one element per GPU lane; Alg. 1: local pairs are mapped to global indices and
+ *     the triplets are summed and compressed ("sparse").
+ * The global matrix is returned as lower-triangular CSR: row = max(E_a, E_b),
+ * col = min(E_a, E_b); columns ascend within a row, so the diagonal is the last entry
+ * of its row.  The pattern is structural: every (row, col) pair that some element
+ * touches is stored, even when its value sums to zero.  Indices are 0-based int32.
+ *
+ * Elements and rules:
+ *   KB_HEX8  8-node trilinear brick, 2x2x2 Gauss-Legendre (points +-1/sqrt(3), weights 1);
+ *            local corners (-1,-1,-1) (1,-1,-1) (1,1,-1) (-1,1,-1) (-1,-1,1) (1,-1,1)
+ *            (1,1,1) (-1,1,1) in natural coordinates.
+ *   KB_TET4  4-node linear tetrahedron, one centroid point with weight 1/6 (exact);
+ *            N0 = 1-r-s-t, N1 = r, N2 = s, N3 = t.
+ * Per-element lower values are packed as p = a*(a+1)/2 + b for 0 <= b <= a < nen.
+ *
+ * Precision modes (value type of vals / per-element outputs in parentheses):
+ *   KB_FP64       all arithmetic in FP64 (double);
+ *   KB_FP32       node coordinates are differenced in FP64 against the element's first
+ *                 node, the rest of the integration runs in FP32; assembly sums in FP64
+ *                 and rounds each entry once (float);
+ *   KB_FP32_FB64  as KB_FP32, but an element whose Jacobian at some integration point
+ *                 has an estimated infinity-norm condition number above tau gets its
+ *                 Jacobian, determinant and inverse in FP64 (float).
+ *
+ * Memory and streams.  Every pointer passed to kb_build_lower_csr,
+ * kb_integrate_lower and kb_assemble_lower_csr is a device pointer (except the
+ * kb_mesh / kb_tuning structs themselves, which are host memory read during the
+ * call).  The caller owns and allocates all memory; the library allocates nothing
+ * and keeps no state between calls.  Work is enqueued on `stream` (a hipStream_t)
+ * and the calls return without synchronising; results are valid once the stream
+ * reaches that point.  Calls that share a workspace must be ordered on one stream.
+ * The output of a call is bitwise deterministic for given inputs and precision.
+ *
+ * Errors.  Host-detectable argument errors are returned immediately (nothing is
+ * enqueued).  Data errors are found on the device and OR-ed into status_dev[0]:
+ * an element with an index error (KB_F_INDEX, KB_F_REPEAT) is excluded from the
+ * matrix; KB_F_INVERTED and KB_F_NONFINITE elements are integrated as given.
+ */
+#ifndef KBUILD_H
+#define KBUILD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KB_VERSION 1
+
+/* element types (value = nodes per element) */
+#define KB_HEX8 8
+#define KB_TET4 4
+
+/* precision modes */
+#define KB_FP64 0
+#define KB_FP32 1
+#define KB_FP32_FB64 2
+
+/* return codes */
+#define KB_OK 0
+#define KB_EINVAL (-1)  /* null pointer, unknown element or precision, negative size  */
+#define KB_ERANGE (-2)  /* n_node or n_elem * nen*(nen+1)/2 does not fit int32 indexing */
+#define KB_ENOSPC (-3)  /* ws_bytes smaller than kb_plan's figure                       */
+#define KB_EHIP (-4)    /* a HIP launch or event call failed                           */
+
+/* device status words: status_dev[KB_STATUS_WORDS] (uint32) */
+#define KB_STATUS_WORDS 4
+/* status_dev[0]: data-error flags */
+#define KB_F_INDEX 1u      /* a node id outside [0, n_node)                           */
+#define KB_F_REPEAT 2u     /* a node id repeated within one element                   */
+#define KB_F_INVERTED 4u   /* Jacobian determinant not > 0 at some integration point  */
+#define KB_F_NONFINITE 8u  /* non-finite coordinate, coefficient or computed value    */
+#define KB_F_CAPACITY 16u  /* nnz > cap: col_idx / vals were not written              */
+/* status_dev[1]: number of elements integrated on the FP64 fallback (KB_FP32_FB64)
+ * status_dev[2], status_dev[3]: reserved, written as 0 */
+
+/* stages recorded into kb_tuning.stage_events (KB_N_STAGES + 1 events) */
+#define KB_N_STAGES 6
+#define KB_STAGE_INIT 0       /* clear counters and status                              */
+#define KB_STAGE_COUNT 1      /* validate connectivity, count contributions per row      */
+#define KB_STAGE_SCAN_ROWS 2  /* exclusive scan of the row counts                         */
+#define KB_STAGE_INTEGRATE 3  /* integrate elements (or read given values) and scatter    */
+#define KB_STAGE_REDUCE 4     /* per row: order by column, sum duplicates                */
+#define KB_STAGE_COMPRESS 5   /* scan of unique counts, row_ptr, col_idx / vals           */
+
+typedef struct {
+  int32_t elem;          /* KB_HEX8 or KB_TET4                                         */
+  int32_t reserved;      /* must be 0                                                   */
+  int64_t n_elem;        /* number of elements (>= 0)                                   */
+  int64_t n_node;        /* number of nodes = matrix dimension (>= 0)                   */
+  const int32_t* conn;   /* device [n_elem][nen] node ids, row-major                    */
+  const double* coords;  /* device [n_node][3] x, y, z, row-major                       */
+  const double* coef;    /* device [n_elem] coefficient c of each element               */
+} kb_mesh;
+
+/* Optional tuning knobs; pass NULL for defaults.  Zero fields mean "default". */
+typedef struct {
+  int32_t block;           /* threads per workgroup of the element kernels (64..1024)   */
+  int32_t rows_per_block;  /* rows per workgroup of the row reduction (power of two)    */
+  float fb_tau;            /* KB_FP32_FB64 condition-number threshold (> 1)             */
+  int32_t reserved;        /* must be 0                                                 */
+  void** stage_events;     /* NULL, or KB_N_STAGES + 1 hipEvent_t: event i is recorded
+                              on the stream before stage i, the last after the final one */
+} kb_tuning;
+
+/*
+ * Size the workspace.  Host only (no device access).  On success *ws_bytes is the
+ * workspace needed by kb_build_lower_csr and kb_assemble_lower_csr for this mesh
+ * shape and precision, and *n_triplets = n_elem * nen*(nen+1)/2, an upper bound on
+ * nnz (so cap = *n_triplets always suffices).  Either output pointer may be NULL.
+ * Only elem, n_elem and n_node of the mesh are read.
+ */
+int kb_plan(const kb_mesh* mesh, int prec, const kb_tuning* tuning, size_t* ws_bytes, int64_t* n_triplets);
+
+/*
+ * Full construction (Alg. 1 with the integration of Alg. 2): integrate the lower
+ * triangle of every element matrix and assemble lower-triangular CSR K.
+ *   ws        device workspace of ws_bytes >= kb_plan's figure (contents scratch)
+ *   row_ptr   device [n_node + 1]; always written unless an argument error is returned
+ *   col_idx   device [cap], vals device [cap] of double (KB_FP64) or float (otherwise);
+ *             written only if nnz <= cap, else KB_F_CAPACITY is set
+ *   nnz_dev   device int64, receives nnz
+ *   status_dev device uint32[KB_STATUS_WORDS], overwritten (see above)
+ *   stream    hipStream_t (NULL = default stream)
+ */
+int kb_build_lower_csr(const kb_mesh* mesh, int prec, const kb_tuning* tuning, void* ws, size_t ws_bytes,
+                       int32_t* row_ptr, int32_t* col_idx, void* vals, int64_t cap, int64_t* nnz_dev,
+                       uint32_t* status_dev, void* stream);
+
+/*
+ * Integration only (Alg. 2): vals device [n_elem][nen*(nen+1)/2] of double (KB_FP64)
+ * or float, element-major, packed lower order.  Elements with index errors get zeros.
+ * No workspace.  status_dev as above.
+ */
+int kb_integrate_lower(const kb_mesh* mesh, int prec, const kb_tuning* tuning, void* vals, uint32_t* status_dev,
+                       void* stream);
+
+/*
+ * Assembly only (Eq. 6 and the "sparse" step of Alg. 1) from given per-element lower
+ * values klow (device [n_elem][nen*(nen+1)/2], double for KB_FP64, float otherwise);
+ * mesh->coords and mesh->coef are not read and may be NULL.  Outputs as for
+ * kb_build_lower_csr.  KB_FP32 and KB_FP32_FB64 behave alike here.
+ */
+int kb_assemble_lower_csr(const kb_mesh* mesh, int prec, const kb_tuning* tuning, const void* klow, void* ws,
+                          size_t ws_bytes, int32_t* row_ptr, int32_t* col_idx, void* vals, int64_t cap,
+                          int64_t* nnz_dev, uint32_t* status_dev, void* stream);
+
+/* Static text for a return code (negative) or a single status flag bit (positive). */
+const char* kb_status_string(int code);
+
+/* KB_VERSION of the loaded library. */
+int kb_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KBUILD_H */

@@ -1,0 +1,104 @@
+"""ctypes binding of ``libkbuild.so`` (argument marshalling only; no compute here)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libkbuild.so")
+
+KB_HEX8, KB_TET4 = 8, 4
+KB_FP64, KB_FP32, KB_FP32_FB64 = 0, 1, 2
+KB_OK, KB_EINVAL, KB_ERANGE, KB_ENOSPC, KB_EHIP = 0, -1, -2, -3, -4
+KB_STATUS_WORDS = 4
+KB_F_INDEX, KB_F_REPEAT, KB_F_INVERTED, KB_F_NONFINITE, KB_F_CAPACITY = 1, 2, 4, 8, 16
+KB_N_STAGES = 6
+STAGE_NAMES = ("init", "count", "scan_rows", "integrate", "reduce", "compress")
+
+# every function declared in include/kbuild.h
+EXPORTS = ("kb_plan", "kb_build_lower_csr", "kb_integrate_lower", "kb_assemble_lower_csr", "kb_status_string",
+           "kb_version")
+
+
+class KbMesh(ctypes.Structure):
+    _fields_ = [
+        ("elem", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("n_elem", ctypes.c_int64),
+        ("n_node", ctypes.c_int64),
+        ("conn", ctypes.c_void_p),
+        ("coords", ctypes.c_void_p),
+        ("coef", ctypes.c_void_p),
+    ]
+
+
+class KbTuning(ctypes.Structure):
+    _fields_ = [
+        ("block", ctypes.c_int32),
+        ("rows_per_block", ctypes.c_int32),
+        ("fb_tau", ctypes.c_float),
+        ("reserved", ctypes.c_int32),
+        ("stage_events", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load the HIP library; raise if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'` "
+                "or `python paper_1501_04784_amd/build.py`")
+        L = ctypes.CDLL(LIB_PATH)
+        p, i32, i64, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_size_t
+        PM, PT = ctypes.POINTER(KbMesh), ctypes.POINTER(KbTuning)
+        L.kb_plan.argtypes = [PM, i32, PT, ctypes.POINTER(sz), ctypes.POINTER(i64)]
+        L.kb_plan.restype = i32
+        L.kb_build_lower_csr.argtypes = [PM, i32, PT, p, sz, p, p, p, i64, p, p, p]
+        L.kb_build_lower_csr.restype = i32
+        L.kb_integrate_lower.argtypes = [PM, i32, PT, p, p, p]
+        L.kb_integrate_lower.restype = i32
+        L.kb_assemble_lower_csr.argtypes = [PM, i32, PT, p, p, sz, p, p, p, i64, p, p, p]
+        L.kb_assemble_lower_csr.restype = i32
+        L.kb_status_string.argtypes = [i32]
+        L.kb_status_string.restype = ctypes.c_char_p
+        L.kb_version.argtypes = []
+        L.kb_version.restype = i32
+        _lib = L
+    return _lib
+
+
+# ---- HIP events (same runtime instance as the library and torch) --------------------
+class HipEvents:
+    """A set of HIP timing events, resolved through the library's own HIP runtime."""
+
+    def __init__(self, n: int):
+        L = lib()
+        self._L = L
+        L.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        L.hipEventCreate.restype = ctypes.c_int
+        L.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+        L.hipEventElapsedTime.restype = ctypes.c_int
+        L.hipEventDestroy.argtypes = [ctypes.c_void_p]
+        L.hipEventDestroy.restype = ctypes.c_int
+        self.handles = []
+        for _ in range(n):
+            h = ctypes.c_void_p()
+            if L.hipEventCreate(ctypes.byref(h)) != 0:
+                raise RuntimeError("hipEventCreate failed")
+            self.handles.append(h.value)
+
+    def elapsed_ms(self, i: int, j: int) -> float:
+        ms = ctypes.c_float(0.0)
+        if self._L.hipEventElapsedTime(ctypes.byref(ms), self.handles[i], self.handles[j]) != 0:
+            raise RuntimeError("hipEventElapsedTime failed")
+        return float(ms.value)
+
+    def close(self):
+        for h in self.handles:
+            self._L.hipEventDestroy(h)
+        self.handles = []

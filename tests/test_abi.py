@@ -1,0 +1,125 @@
+"""Host-side checks of the C ABI (no GPU needed): exports, planning, argument errors."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1501_04784_amd import _lib
+from paper_1501_04784_amd._lib import KbMesh, KbTuning
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "kbuild.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\*?\s+\**(kb_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_library_exports_every_declared_function():
+    names = declared_functions()
+    assert set(names) == set(_lib.EXPORTS)
+    L = _lib.lib()
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_header_constants_match_binding():
+    src = open(HEADER).read()
+    consts = dict(re.findall(r"#define\s+(KB_\w+)\s+\(?(-?\d+)u?\)?", src))
+    for name in ("KB_HEX8", "KB_TET4", "KB_FP64", "KB_FP32", "KB_FP32_FB64", "KB_OK", "KB_EINVAL", "KB_ERANGE",
+                 "KB_ENOSPC", "KB_EHIP", "KB_STATUS_WORDS", "KB_F_INDEX", "KB_F_REPEAT", "KB_F_INVERTED",
+                 "KB_F_NONFINITE", "KB_F_CAPACITY", "KB_N_STAGES"):
+        assert int(consts[name]) == getattr(_lib, name), name
+
+
+def test_struct_layout():
+    assert ctypes.sizeof(KbMesh) == 48
+    assert KbMesh.conn.offset == 24 and KbMesh.coef.offset == 40
+    assert ctypes.sizeof(KbTuning) == 24 and KbTuning.stage_events.offset == 16
+
+
+def _plan(elem, nel, nn, prec=0, tuning=None):
+    m = KbMesh(elem, 0, nel, nn, None, None, None)
+    ws = ctypes.c_size_t(0)
+    nt = ctypes.c_int64(0)
+    tu = ctypes.byref(tuning) if tuning is not None else None
+    rc = _lib.lib().kb_plan(ctypes.byref(m), prec, tu, ctypes.byref(ws), ctypes.byref(nt))
+    return rc, ws.value, nt.value
+
+
+def test_version_and_strings():
+    L = _lib.lib()
+    assert L.kb_version() == 1
+    assert L.kb_status_string(0) == b"ok"
+    assert L.kb_status_string(-3) == b"workspace too small"
+    assert L.kb_status_string(16) == b"nnz exceeds capacity"
+    assert L.kb_status_string(12345) == b"unknown status"
+
+
+@pytest.mark.parametrize("elem,te", [(8, 36), (4, 10)])
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_plan_sizes(elem, te, prec):
+    rc, ws, nt = _plan(elem, 1000, 1331, prec)
+    assert rc == 0 and nt == 1000 * te
+    vb = 8 if prec == 0 else 4
+    # at least: element values, two (col, value) lists, four per-node int arrays
+    assert ws >= nt * (vb + 2 * (4 + vb)) + 4 * 4 * 1331
+    assert ws % 256 == 0
+
+
+def test_plan_empty_mesh():
+    rc, ws, nt = _plan(4, 0, 0)
+    assert rc == 0 and nt == 0
+
+
+def test_plan_errors():
+    L = _lib.lib()
+    assert L.kb_plan(None, 0, None, None, None) == _lib.KB_EINVAL
+    assert _plan(5, 10, 10)[0] == _lib.KB_EINVAL
+    assert _plan(8, 10, 10, prec=3)[0] == _lib.KB_EINVAL
+    assert _plan(8, -1, 10)[0] == _lib.KB_EINVAL
+    assert _plan(8, 10, -1)[0] == _lib.KB_EINVAL
+    assert _plan(8, 2**31 // 36 + 1, 10)[0] == _lib.KB_ERANGE
+    assert _plan(4, 10, 2**31)[0] == _lib.KB_ERANGE
+    assert _plan(4, 2**31 // 10, 10)[0] == 0
+    assert _plan(8, 10, 10, tuning=KbTuning(100, 0, 0.0, 0, None))[0] == _lib.KB_EINVAL  # block not multiple of 64
+    assert _plan(8, 10, 10, tuning=KbTuning(0, 3, 0.0, 0, None))[0] == _lib.KB_EINVAL  # not a power of two
+    assert _plan(8, 10, 10, tuning=KbTuning(0, 0, 0.5, 0, None))[0] == _lib.KB_EINVAL  # tau <= 1
+    assert _plan(8, 10, 10, tuning=KbTuning(0, 0, 0.0, 1, None))[0] == _lib.KB_EINVAL  # reserved
+    assert _plan(8, 10, 10, tuning=KbTuning(512, 64, 8.0, 0, None))[0] == 0
+
+
+def test_build_argument_errors_return_before_any_launch():
+    """Null pointers and short workspaces are rejected on the host (no device touched)."""
+    L = _lib.lib()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails validation first
+    m = KbMesh(8, 0, 10, 20, 0x1000, 0x1000, 0x1000)
+    rc, ws, nt = _plan(8, 10, 20)
+    args = dict(ws=fake, ws_bytes=ws, row_ptr=fake, col=fake, vals=fake, cap=nt, nnz=fake, status=fake)
+
+    def call(**kw):
+        a = {**args, **kw}
+        return L.kb_build_lower_csr(ctypes.byref(m), 0, None, a["ws"], a["ws_bytes"], a["row_ptr"], a["col"],
+                                    a["vals"], a["cap"], a["nnz"], a["status"], None)
+
+    assert call(ws_bytes=ws - 1) == _lib.KB_ENOSPC
+    assert call(row_ptr=None) == _lib.KB_EINVAL
+    assert call(nnz=None) == _lib.KB_EINVAL
+    assert call(status=None) == _lib.KB_EINVAL
+    assert call(cap=-1) == _lib.KB_EINVAL
+    assert call(col=None) == _lib.KB_EINVAL
+    assert call(ws=None) == _lib.KB_EINVAL
+    m.conn = None
+    assert call() == _lib.KB_EINVAL
+    m.conn = 0x1000
+    m.coords = None
+    assert call() == _lib.KB_EINVAL
+    # assembly-only path does not need coordinates, but needs values
+    assert L.kb_assemble_lower_csr(ctypes.byref(m), 0, None, None, fake, ws, fake, fake, fake, nt, fake, fake,
+                                   None) == _lib.KB_EINVAL
+    assert L.kb_integrate_lower(ctypes.byref(m), 0, None, fake, None, None) == _lib.KB_EINVAL

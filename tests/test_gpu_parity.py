@@ -1,0 +1,227 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle, on the GPU.
+
+Pattern (row_ptr, col_idx) must match bit for bit; values within the scaled
+tolerance max |dK_ij| / sqrt(K_ii K_jj) of 1e-12 (FP64) and 5e-6 (FP32 with FP64
+fallback).  Sizes are chosen so that the oracle finishes in about a second while
+the launch still spans many workgroups and ends in a ragged tail.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import meshgen
+import oracle
+import paper_1501_04784_amd as kb
+from tests.gpu_common import TOL, elem_scaled_error, gpu_build, np_csr, say, to_dev
+from tests.helpers import scaled_error
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # collected on CPU only when -m gpu is asked for explicitly
+    pytest.skip("no GPU", allow_module_level=True)
+
+PRECS = ["fp64", "fp32fb64", "fp32"]
+
+
+def small_meshes():
+    return {
+        "c1_hex10": meshgen.config_mesh(1),
+        "c2_hex13": meshgen.config_mesh(2, n=13),
+        "c3_tet9": meshgen.config_mesh(3, n=9),
+        "c5_hex16": meshgen.config_mesh(5, n=16),
+        "tet_box_7x5x3": meshgen.box_mesh(4, 7, 5, 3, jitter=0.2, coef=(0.1, 10), permute_nodes=True,
+                                          permute_elems=True, seed=21),
+        "hex_box_1x1x1": meshgen.box_mesh(8, 1, jitter=0.0, coef=2.0, seed=0),
+        "tet_single": meshgen.Mesh(4, np.array([[0, 1, 2, 3]], np.int32),
+                                   np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], float), np.array([1.5])),
+    }
+
+
+MESHES = small_meshes()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("name", sorted(MESHES))
+def test_integrate_parity(name, prec):
+    m = MESHES[name]
+    say(f"[integrate] {name} {prec} nel={m.n_elem}")
+    conn, coords, coef = to_dev(m)
+    k, status = kb.integrate_lower(conn, coords, coef, m.elem, prec=prec)
+    kref, flags = oracle.integrate_lower(m.elem, m.conn, m.coords, m.coef)
+    assert flags == 0
+    err = elem_scaled_error(k.cpu().numpy().astype(np.float64), kref, m.elem)
+    say(f"  element scaled error {err:.3e}")
+    assert err <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("name", sorted(MESHES))
+def test_build_parity(name, prec):
+    m = MESHES[name]
+    say(f"[build] {name} {prec} nel={m.n_elem} nn={m.n_node}")
+    r = gpu_build(m, prec)
+    rp, col, val = np_csr(r)
+    orp, ocol, oval, oflags = oracle.build_mesh(m)
+    assert oflags == 0 and r.flags == 0
+    np.testing.assert_array_equal(rp, orp)
+    np.testing.assert_array_equal(col, ocol)
+    err = scaled_error(orp, ocol, val, oval)
+    say(f"  nnz={len(col)} scaled error {err:.3e} fallback={r.n_fallback}")
+    assert err <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32fb64"])
+@pytest.mark.parametrize("elem,n", [(8, 40), (4, 30)])
+def test_build_parity_medium(elem, n, prec):
+    """64k bricks / 162k tets with random numbering: many row blocks, exact pattern."""
+    cid = 2 if elem == 8 else 3
+    m = meshgen.config_mesh(cid, n=n)
+    say(f"[build-medium] elem={elem} n={n} {prec} nel={m.n_elem}")
+    r = gpu_build(m, prec)
+    rp, col, val = np_csr(r)
+    orp, ocol, oval, _ = oracle.build_mesh(m)
+    np.testing.assert_array_equal(rp, orp)
+    np.testing.assert_array_equal(col, ocol)
+    err = scaled_error(orp, ocol, val, oval)
+    say(f"  nnz={len(col)} scaled error {err:.3e} fallback={r.n_fallback}")
+    assert err <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", ["c2_hex13", "c3_tet9"])
+def test_assemble_parity(name, prec):
+    """Assembly alone from the oracle's element values (cast to the value type)."""
+    m = MESHES[name]
+    kref, _ = oracle.integrate_lower(m.elem, m.conn, m.coords, m.coef)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    klow = torch.from_numpy(kref).to(dt).cuda()
+    conn = torch.from_numpy(m.conn).cuda()
+    r = kb.assemble_lower_csr(conn, m.n_node, klow, m.elem, prec=prec)
+    rp, col, val = np_csr(r)
+    kin = klow.cpu().numpy().astype(np.float64)
+    orp, ocol, oval, _ = oracle.assemble_lower_csr(m.elem, m.conn, m.n_node, kin)
+    np.testing.assert_array_equal(rp, orp)
+    np.testing.assert_array_equal(col, ocol)
+    # same inputs: only summation order and the final rounding differ
+    assert scaled_error(orp, ocol, val, oval) <= (1e-15 if prec == "fp64" else 1e-7)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32fb64"])
+def test_bitwise_determinism(prec):
+    m = meshgen.config_mesh(3, n=20)
+    a = np_csr(gpu_build(m, prec))
+    b = np_csr(gpu_build(m, prec))
+    for x, y in zip(a, b):
+        assert x.tobytes() == y.tobytes()
+
+
+def test_empty_mesh():
+    m = meshgen.Mesh(4, np.zeros((0, 4), np.int32), np.zeros((5, 3)), np.zeros(0))
+    conn, coords, coef = to_dev(m)
+    r = kb.build_lower_csr(conn, coords, coef, 4, prec="fp64")
+    assert r.nnz == 0
+    assert r.row_ptr.cpu().tolist() == [0] * 6
+
+
+def test_unused_nodes_have_empty_rows():
+    m = meshgen.box_mesh(4, 3, jitter=0.1, seed=9)
+    coords = np.vstack([m.coords, np.zeros((4, 3))])  # four nodes no element touches
+    m2 = meshgen.Mesh(4, m.conn, coords, m.coef)
+    r = gpu_build(m2, "fp64")
+    rp, col, val = np_csr(r)
+    orp, ocol, oval, _ = oracle.build_mesh(m2)
+    np.testing.assert_array_equal(rp, orp)
+    assert np.all(np.diff(rp[-5:]) == 0)
+
+
+def _fan(n_tets, center_last, seed=0):
+    """n_tets tets sharing one node: its row (or diagonal) collects every element."""
+    rng = np.random.default_rng(seed)
+    nn = 1 + 3 * n_tets
+    X = rng.standard_normal((nn, 3))
+    X[0] = 0.0
+    conn = np.zeros((n_tets, 4), np.int32)
+    for t in range(n_tets):
+        conn[t] = [0, 1 + 3 * t, 2 + 3 * t, 3 + 3 * t]
+        M = np.hstack([np.ones((4, 1)), X[conn[t]]])
+        if np.linalg.det(M) < 0:
+            conn[t, [2, 3]] = conn[t, [3, 2]]
+    if center_last:
+        # relabel: centre gets the largest id, so its row holds 4 entries per element
+        perm = np.roll(np.arange(nn), -1)  # old 0 -> nn-1, old i -> i-1
+        newX = np.empty_like(X)
+        newX[perm] = X
+        conn = perm[conn].astype(np.int32)
+        X = newX
+    return meshgen.Mesh(4, conn, X, np.exp(rng.uniform(-2, 2, n_tets)))
+
+
+@pytest.mark.parametrize("center_last", [False, True])
+@pytest.mark.parametrize("prec", ["fp64", "fp32fb64"])
+def test_heavy_row(center_last, prec):
+    """A node shared by 5000 elements: its row exceeds one row block's LDS capacity."""
+    m = _fan(5000, center_last)
+    r = gpu_build(m, prec)
+    rp, col, val = np_csr(r)
+    orp, ocol, oval, _ = oracle.build_mesh(m)
+    np.testing.assert_array_equal(rp, orp)
+    np.testing.assert_array_equal(col, ocol)
+    assert scaled_error(orp, ocol, val, oval) <= TOL[prec]
+
+
+def test_capacity_flag():
+    m = meshgen.config_mesh(1)
+    r = gpu_build(m, "fp64", cap=1000, check=False)
+    assert r.flags & kb._lib.KB_F_CAPACITY
+    assert r.nnz == 15561
+    orp = oracle.build_mesh(m)[0]
+    np.testing.assert_array_equal(r.row_ptr.cpu().numpy(), orp)
+
+
+@pytest.mark.parametrize("kind", ["index", "negative", "repeat", "inverted", "nan", "inf_coef"])
+def test_data_error_flags(kind):
+    m = meshgen.box_mesh(4, 4, jitter=0.1, coef=(0.5, 2.0), permute_nodes=True, seed=5)
+    conn, coords, coef = m.conn.copy(), m.coords.copy(), m.coef.copy()
+    want = {"index": kb._lib.KB_F_INDEX, "negative": kb._lib.KB_F_INDEX, "repeat": kb._lib.KB_F_REPEAT,
+            "inverted": kb._lib.KB_F_INVERTED, "nan": kb._lib.KB_F_NONFINITE, "inf_coef": kb._lib.KB_F_NONFINITE}[kind]
+    if kind == "index":
+        conn[17, 2] = m.n_node
+    elif kind == "negative":
+        conn[3, 0] = -5
+    elif kind == "repeat":
+        conn[8, 3] = conn[8, 1]
+    elif kind == "inverted":
+        conn[11, [2, 3]] = conn[11, [3, 2]]
+    elif kind == "nan":
+        coords[conn[4, 2], 0] = np.nan
+    else:
+        coef[9] = np.inf
+    bad = meshgen.Mesh(4, conn, coords, coef)
+    for prec in PRECS:
+        r = gpu_build(bad, prec, check=False)
+        assert r.flags & want, (kind, prec, r.flags)
+        oflags = oracle.build_mesh(bad)[3]
+        assert oflags & want
+        if kind in ("index", "negative", "repeat"):
+            # the offending element is excluded, exactly as in the oracle
+            orp, ocol, oval, _ = oracle.build_mesh(bad)
+            rp, col, val = np_csr(r)
+            np.testing.assert_array_equal(rp, orp)
+            np.testing.assert_array_equal(col, ocol)
+            assert scaled_error(orp, ocol, val, oval) <= TOL[prec]
+        with pytest.raises(kb.KBuildError):
+            gpu_build(bad, prec, check=True)
+
+
+def test_fallback_fires_on_distorted_mesh():
+    """Heavily distorted bricks trigger the FP64 Jacobian path and stay within tolerance."""
+    m = meshgen.box_mesh(8, 10, jitter=0.45, coef=(1e-2, 1e2), permute_nodes=True, seed=13)
+    r = gpu_build(m, "fp32fb64", allow_flags=kb._lib.KB_F_INVERTED)
+    orp, ocol, oval, _ = oracle.build_mesh(m)
+    rp, col, val = np_csr(r)
+    np.testing.assert_array_equal(col, ocol)
+    say(f"  fallback elements {r.n_fallback} of {m.n_elem}")
+    assert r.n_fallback > 0
+    assert scaled_error(orp, ocol, val, oval) <= TOL["fp32fb64"]
