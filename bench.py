@@ -36,9 +36,10 @@ WORKLOADS = {
 def algorithmic_bytes(elem: int, n_elem: int, n_node: int, nnz: int, prec: str) -> dict:
     """Compulsory HBM bytes of each stage and of the whole path (per launch).
 
-    Inputs read once, outputs written once; the per-element lower values (T_e values)
-    are written once and read once, and the row-ordered (col, value) list is written
-    once and read once; coordinates are counted once per node.
+    Per stage: its inputs read once and its outputs written once, in the formats the
+    stage exchanges ((8-byte key, value) pairs between the partition passes).  For the
+    path: E, c and C read once (coordinates once per node), the lower values written
+    once and read once, CSR written once.
     """
     vb = 8 if prec == "fp64" else 4
     nen = elem
@@ -48,12 +49,11 @@ def algorithmic_bytes(elem: int, n_elem: int, n_node: int, nnz: int, prec: str) 
     coef = 8 * n_elem
     coords = 24 * n_node
     b = {
-        "count": conn + 4 * n_node,                              # E in, row counts out
-        "scan_rows": 8 * n_node,                                  # counts in, starts out
-        "integrate": conn + coef + coords + vb * T,               # E, c, C in; lower values out
-        "scatter": conn + vb * T + 4 * n_node + (4 + vb) * T,     # E, values, row starts in; (col, val) out
-        "reduce": 4 * n_node + (4 + vb) * T + (4 + vb) * nnz + 4 * n_node,
-        "compress": 8 * n_node + 2 * (4 + vb) * nnz + 4 * n_node,
+        "count": conn,                                            # E in (histogram out is small)
+        "integrate": conn + coef + coords + (8 + vb) * T,         # E, c, C in; (key, value) pairs out
+        "partition": 8 * T + 2 * (8 + vb) * T,                    # keys for the histogram, pairs in and out
+        "reduce": (8 + vb) * T + (4 + vb) * nnz + 4 * n_node,     # pairs in; unique entries, row counts out
+        "compress": 2 * (4 + vb) * nnz + 8 * n_node,              # unique entries in, CSR out
     }
     # the path as a whole: E, c, C in once, lower values once out and in, CSR out
     b["path"] = conn + coef + coords + 2 * vb * T + (4 + vb) * nnz + 4 * (n_node + 1)

@@ -87,13 +87,14 @@ extern "C" {
  * status_dev[2], status_dev[3]: reserved, written as 0 */
 
 /* stages recorded into kb_tuning.stage_events (KB_N_STAGES + 1 events) */
-#define KB_N_STAGES 6
-#define KB_STAGE_INIT 0       /* clear counters and status                              */
-#define KB_STAGE_COUNT 1      /* validate connectivity, count contributions per row      */
-#define KB_STAGE_SCAN_ROWS 2  /* exclusive scan of the row counts                         */
-#define KB_STAGE_INTEGRATE 3  /* integrate elements (or read given values) and scatter    */
-#define KB_STAGE_REDUCE 4     /* per row: order by column, sum duplicates                */
-#define KB_STAGE_COMPRESS 5   /* scan of unique counts, row_ptr, col_idx / vals           */
+#define KB_N_STAGES 7
+#define KB_STAGE_INIT 0       /* clear status                                             */
+#define KB_STAGE_COUNT 1      /* validate connectivity, pairs per row bucket per tile      */
+#define KB_STAGE_OFFSETS 2    /* scan: each tile's write offset in each bucket             */
+#define KB_STAGE_INTEGRATE 3  /* integrate (or read given values), partition by bucket    */
+#define KB_STAGE_PARTITION 4  /* partition each bucket into sub-buckets                    */
+#define KB_STAGE_REDUCE 5     /* per sub-bucket: group equal (row, col), ordered FP64 sums */
+#define KB_STAGE_COMPRESS 6   /* scan of unique counts, row_ptr, col_idx / vals            */
 
 typedef struct {
   int32_t elem;          /* KB_HEX8 or KB_TET4                                         */
@@ -107,10 +108,10 @@ typedef struct {
 
 /* Optional tuning knobs; pass NULL for defaults.  Zero fields mean "default". */
 typedef struct {
-  int32_t block;           /* threads per workgroup of the element kernels (64..1024)   */
-  int32_t rows_per_block;  /* rows per workgroup of the row reduction (power of two)    */
+  int32_t block;           /* threads per workgroup of kb_integrate_lower (64..1024)    */
+  int32_t bucket_bits;     /* log2 rows per first-level bucket (0 = from mesh shape)    */
   float fb_tau;            /* KB_FP32_FB64 condition-number threshold (> 1)             */
-  int32_t reserved;        /* must be 0                                                 */
+  int32_t sub_bits;        /* log2 rows per sub-bucket, <= bucket_bits and <= 8 (0 = auto) */
   void** stage_events;     /* NULL, or KB_N_STAGES + 1 hipEvent_t: event i is recorded
                               on the stream before stage i, the last after the final one */
 } kb_tuning;

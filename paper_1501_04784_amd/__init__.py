@@ -66,11 +66,12 @@ def _mesh(elem, n_elem, n_node, conn=None, coords=None, coef=None) -> KbMesh:
 @dataclass
 class Tuning:
     block: int = 0
-    rows_per_block: int = 0
+    bucket_bits: int = 0
     fb_tau: float = 0.0
+    sub_bits: int = 0
 
     def to_c(self, events=None) -> KbTuning:
-        return KbTuning(int(self.block), int(self.rows_per_block), float(self.fb_tau), 0, events)
+        return KbTuning(int(self.block), int(self.bucket_bits), float(self.fb_tau), int(self.sub_bits), events)
 
 
 def plan(elem: int, n_elem: int, n_node: int, prec="fp64", tuning: Tuning | None = None):

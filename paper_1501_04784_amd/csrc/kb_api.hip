@@ -6,6 +6,9 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
+
+#include "kb_assemble.hpp"
 #include "kb_kernels.hpp"
 #include "kbuild.h"
 
@@ -16,20 +19,34 @@ using namespace kb;
 constexpr size_t kAlign = 256;
 constexpr float kDefaultTau = 16.0f;
 constexpr int kDefaultBlock = 256;
+constexpr int kSeg = 4096;         // pairs per pass-2 segment
+constexpr int kTargetBuckets = 512;  // first-level buckets (pass-1 run length)
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 struct Plan {
-  int nen = 0, te = 0, prec = 0, block = kDefaultBlock, rb = 16;
+  int nen = 0, te = 0, prec = 0, block = kDefaultBlock;
   float tau = kDefaultTau;
   int64_t nel = 0, nn = 0, T = 0;
   size_t vbytes = 8;
+  // assembly geometry
+  int s1 = 0, s2 = 0, p2 = 1, nb = 0;  // bucket / sub-bucket shifts, sub-buckets per bucket, buckets
+  int colbits = 1;                     // bits of a column index
+  int tile = 0;                        // elements (= threads) per pass-1 workgroup
+  int64_t ntiles = 0, nsub = 0, nhist = 0, nseg_max = 0;
+  size_t lds1 = 0, lds2 = 0;
   // workspace offsets
-  size_t o_rowcnt = 0, o_rowstart = 0, o_cursor = 0, o_uniq = 0, o_klow = 0, o_icol = 0, o_ival = 0, o_rcol = 0,
-         o_rval = 0, o_part = 0, total = 0;
+  size_t o_hist = 0, o_histT = 0, o_part = 0, o_total = 0, o_bstart = 0, o_segbase = 0, o_hist2 = 0, o_emax = 0,
+         o_row1 = 0, o_col1 = 0, o_val1 = 0, o_key2 = 0, o_val2 = 0, o_sbb = 0, o_ucnt = 0, o_usub = 0, o_ubase = 0,
+         total = 0;
 };
 
-int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
+int ilog2_ceil(int64_t x) {
+  int k = 0;
+  while (((int64_t)1 << k) < x) ++k;
+  return k;
+}
 
 int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p) {
   if (!m) return KB_EINVAL;
@@ -45,8 +62,8 @@ int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p) {
   if (p->nel > (int64_t)INT32_MAX / p->te) return KB_ERANGE;
   p->T = p->nel * p->te;
   p->vbytes = prec == KB_FP64 ? 8 : 4;
+  int bucket_bits = 0, sub_bits = 0;
   if (tu) {
-    if (tu->reserved != 0) return KB_EINVAL;
     if (tu->block) {
       if (tu->block < 64 || tu->block > 1024 || (tu->block & 63)) return KB_EINVAL;
       p->block = tu->block;
@@ -55,36 +72,76 @@ int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p) {
       if (!(tu->fb_tau > 1.0f)) return KB_EINVAL;
       p->tau = tu->fb_tau;
     }
-    if (tu->rows_per_block) {
-      if (tu->rows_per_block < 1 || tu->rows_per_block > 1024 || (tu->rows_per_block & (tu->rows_per_block - 1)))
-        return KB_EINVAL;
-      p->rb = tu->rows_per_block;
-    }
+    if (tu->sub_bits < 0 || tu->sub_bits > 8 || tu->bucket_bits < 0 || tu->bucket_bits > 30) return KB_EINVAL;
+    if (tu->bucket_bits && tu->sub_bits && tu->sub_bits > tu->bucket_bits) return KB_EINVAL;
+    if (tu->bucket_bits && tu->bucket_bits - (tu->sub_bits ? tu->sub_bits : 0) > 12) return KB_EINVAL;
+    bucket_bits = tu->bucket_bits;
+    sub_bits = tu->sub_bits;
   }
-  if (!tu || !tu->rows_per_block) {
-    // about half of the LDS capacity per row block on average
-    const double avg = p->nn > 0 ? (double)p->T / (double)p->nn : 1.0;
-    int rb = 1;
-    while (rb < 1024 && (2.0 * rb) * avg <= 0.5 * kReduceCap) rb *= 2;
-    p->rb = rb;
+  // sub-buckets: about a third of the pass-3 hash table of distinct entries on average;
+  // distinct entries per row estimated from the pairs per row and the typical number
+  // of elements sharing an entry (about 7 for tetrahedra, 2.5 for bricks)
+  p->colbits = 1;
+  while (((int64_t)1 << p->colbits) < p->nn) ++p->colbits;
+  const double avg = p->nn > 0 ? (double)p->T / (double)p->nn : 1.0;
+  const double u_row = std::max(1.0, avg / (p->nen == 4 ? 7.4 : 2.5));
+  const int s2_max = std::min(8, 31 - p->colbits);
+  if (sub_bits) {
+    if (sub_bits > s2_max) return KB_EINVAL;
+    p->s2 = sub_bits;
+  } else {
+    int s2 = 0;
+    while (s2 < s2_max && ((double)(1 << (s2 + 1))) * u_row <= 0.35 * kHT3) ++s2;
+    p->s2 = s2;
   }
+  if (bucket_bits) {
+    p->s1 = bucket_bits < p->s2 ? p->s2 : bucket_bits;
+  } else {
+    const int64_t nsub_min = div_up(p->nn > 0 ? p->nn : 1, (int64_t)1 << p->s2);
+    int d = ilog2_ceil(div_up(nsub_min, kTargetBuckets));
+    if (d > 10) d = 10;
+    p->s1 = p->s2 + d;
+  }
+  if (p->s1 - p->s2 > 10) return KB_EINVAL;
+  p->p2 = 1 << (p->s1 - p->s2);
+  p->nb = (int)div_up(p->nn, (int64_t)1 << p->s1);
+  p->nsub = (int64_t)p->nb * p->p2;
+  // pass-1 tiles: one element per lane, pairs staged in LDS as (8-byte key, value)
+  if (p->nen == 4)
+    p->tile = prec == KB_FP64 ? 768 : 1024;
+  else
+    p->tile = prec == KB_FP64 ? 192 : 256;
+  p->ntiles = div_up(p->nel, p->tile);
+  p->nhist = (int64_t)p->nb * p->ntiles;
+  p->nseg_max = div_up(p->T, kSeg) + p->nb;
+  p->lds1 = (size_t)p->tile * p->te * (8 + p->vbytes) + 3 * 4 * (size_t)p->nb + 4 * (p->tile / 64 + 2);
+  p->lds2 = (size_t)kSeg * (p->vbytes + 4 + 2) + 3 * 4 * (size_t)p->p2 + 4 * 5;
+  if (p->lds1 > 163840 || p->lds2 > 163840) return KB_EINVAL;
   size_t off = 0;
-  auto take = [&](size_t bytes) {
+  auto take = [&](size_t bytes) {  // every region at least one aligned block
     size_t o = off;
-    off = align_up(off + bytes);
+    off = align_up(off + (bytes > 0 ? bytes : 1));
     return o;
   };
-  const size_t nn = (size_t)p->nn, T = (size_t)p->T;
-  p->o_rowcnt = take(4 * nn);
-  p->o_rowstart = take(4 * (nn + 1));
-  p->o_cursor = take(4 * nn);
-  p->o_uniq = take(4 * nn);
-  p->o_klow = take(p->vbytes * T);
-  p->o_icol = take(4 * T);
-  p->o_ival = take(p->vbytes * T);
-  p->o_rcol = take(4 * T);
-  p->o_rval = take(p->vbytes * T);
-  p->o_part = take(4 * (size_t)(div_up(p->nn + 1, kScanChunk) + 1));
+  const size_t T = (size_t)p->T;
+  const int64_t scan_n = std::max(std::max(p->nhist, p->nseg_max * p->p2), p->nsub + 1);
+  p->o_hist = take(4 * (size_t)p->nhist);
+  p->o_histT = take(4 * (size_t)p->nhist);
+  p->o_part = take(4 * (size_t)(div_up(scan_n, kScanChunk) + 1));
+  p->o_total = take(8);
+  p->o_bstart = take(4 * ((size_t)p->nb + 1));
+  p->o_segbase = take(4 * ((size_t)p->nb + 1));
+  p->o_hist2 = take(4 * (size_t)(p->nseg_max * p->p2));
+  p->o_emax = take(4);
+  p->o_row1 = take(4 * T);
+  p->o_col1 = take(4 * T);
+  p->o_val1 = take(p->vbytes * T);
+  p->o_key2 = take(4 * T);
+  p->o_val2 = take(p->vbytes * T);
+  p->o_sbb = take(4 * ((size_t)p->nsub + 1));
+  p->o_ucnt = take(4 * (size_t)p->nn);
+  p->o_usub = take(4 * ((size_t)p->nsub + 1));
+  p->o_ubase = take(4 * ((size_t)p->nsub + 1));
   p->total = off;
   return KB_OK;
 }
@@ -110,7 +167,7 @@ struct Events {
 
 unsigned grid_for(int64_t n, int block) { return (unsigned)div_up(n, block); }
 
-// exclusive scan in[0..n) -> out[0..n], total64 optional
+// exclusive scan in[0..n) -> out[0..n], total64 optional (in-place allowed)
 int scan(const int32_t* in, int64_t n, int32_t* part, int32_t* out, int64_t* total64, hipStream_t s) {
   if (n == 0) {
     k_scan_empty<<<1, 1, 0, s>>>(out, total64);
@@ -127,33 +184,82 @@ int scan(const int32_t* in, int64_t n, int32_t* part, int32_t* out, int64_t* tot
   return KB_OK;
 }
 
-void fill(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
-  if (n <= 0) return;
-  unsigned g = (unsigned)div_up(n, 256);
-  if (g > 4096) g = 4096;
-  k_fill_i32<<<g, 256, 0, s>>>(p, n, v);
+int transpose(const uint32_t* in, uint32_t* out, int64_t rows, int64_t cols, hipStream_t s) {
+  if (rows == 0 || cols == 0) return KB_OK;
+  dim3 g((unsigned)div_up(cols, 32), (unsigned)div_up(rows, 32));
+  k_transpose<<<g, 256, 0, s>>>(in, out, rows, cols);
+  KB_LAUNCH_CHECK();
+  return KB_OK;
+}
+
+template <typename K>
+bool set_lds(K kernel, size_t bytes) {
+  return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) ==
+         hipSuccess;
+}
+
+template <int NEN, Prec P, bool FROM_VALUES>
+int launch_pass1(const Plan& p, const kb_mesh* m, const void* klow, unsigned char* ws, uint32_t* status,
+                 hipStream_t s) {
+  using V = typename PrecTraits<P>::V;
+  constexpr int BLOCK = NEN == 4 ? (P == Prec::F64 ? 768 : 1024) : (P == Prec::F64 ? 192 : 256);
+  if (p.tile != BLOCK) return KB_EINVAL;
+  auto kern = k_pass1<NEN, P, FROM_VALUES, BLOCK>;
+  if (!set_lds(kern, p.lds1)) return KB_EHIP;
+  kern<<<(unsigned)p.ntiles, BLOCK, p.lds1, s>>>(m->conn, m->coords, m->coef, (const V*)klow, p.nel, p.nn, p.tau,
+                                                p.s1, p.nb, (const uint32_t*)(ws + p.o_hist),
+                                                (uint32_t*)(ws + p.o_row1), (uint32_t*)(ws + p.o_col1),
+                                                (V*)(ws + p.o_val1), (uint32_t*)(ws + p.o_emax), status);
+  KB_LAUNCH_CHECK();
+  return KB_OK;
 }
 
 template <typename V>
-int reduce_and_compress(const Plan& p, unsigned char* ws, int32_t* row_ptr, int32_t* col_idx, V* vals, int64_t cap,
-                        int64_t* nnz_dev, uint32_t* status, Events& ev, hipStream_t s) {
-  auto* rowstart = (int32_t*)(ws + p.o_rowstart);
-  auto* uniq = (int32_t*)(ws + p.o_uniq);
-  auto* icol = (int32_t*)(ws + p.o_icol);
-  auto* ival = (V*)(ws + p.o_ival);
-  auto* rcol = (int32_t*)(ws + p.o_rcol);
-  auto* rval = (V*)(ws + p.o_rval);
+int assemble_tail(const Plan& p, unsigned char* ws, int32_t* row_ptr, int32_t* col_idx, V* vals, int64_t cap,
+                  int64_t* nnz_dev, uint32_t* status, Events& ev, hipStream_t s) {
+  auto* bstart = (uint32_t*)(ws + p.o_bstart);
+  auto* segbase = (uint32_t*)(ws + p.o_segbase);
+  auto* hist2 = (uint32_t*)(ws + p.o_hist2);
+  auto* emax = (uint32_t*)(ws + p.o_emax);
+  auto* row1 = (uint32_t*)(ws + p.o_row1);
+  auto* col1 = (uint32_t*)(ws + p.o_col1);
+  auto* val1 = (V*)(ws + p.o_val1);
+  auto* key2 = (uint32_t*)(ws + p.o_key2);
+  auto* val2 = (V*)(ws + p.o_val2);
+  auto* sbb = (uint32_t*)(ws + p.o_sbb);
+  auto* ucnt = (int32_t*)(ws + p.o_ucnt);
+  auto* usub = (uint32_t*)(ws + p.o_usub);
+  auto* ubase = (uint32_t*)(ws + p.o_ubase);
   auto* part = (int32_t*)(ws + p.o_part);
+  // pass-3 output reuses the pass-1 buffers (dead after pass 2)
+  auto* tcol = (int32_t*)row1;
+  auto* tval = val1;
+  KB_TRY(ev.rec(KB_STAGE_PARTITION));
+  if (p.nb > 0) {
+    const unsigned gs = (unsigned)p.nseg_max;
+    k_hist2<kSeg><<<gs, 256, 4 * (size_t)p.p2, s>>>(row1, bstart, segbase, p.nb, p.s2, p.p2, hist2);
+    KB_LAUNCH_CHECK();
+    KB_TRY(scan((const int32_t*)hist2, p.nseg_max * p.p2, part, (int32_t*)hist2, nullptr, s));
+    k_subbucket_starts<<<grid_for(p.nsub + 1, 256), 256, 0, s>>>(hist2, bstart, segbase, p.nb, p.p2, sbb);
+    KB_LAUNCH_CHECK();
+    auto k2 = k_scatter2<V, kSeg>;
+    if (!set_lds(k2, p.lds2)) return KB_EHIP;
+    k2<<<gs, 256, p.lds2, s>>>(row1, col1, val1, bstart, segbase, hist2, p.nb, p.s2, p.p2, p.colbits, key2, val2);
+    KB_LAUNCH_CHECK();
+  }
   KB_TRY(ev.rec(KB_STAGE_REDUCE));
-  if (p.nn > 0) {
-    const size_t lds = (size_t)kReduceCap * (sizeof(V) + 4 + 2) + 4 * (size_t)(p.rb + 1);
-    k_row_reduce<V><<<grid_for(p.nn, p.rb), kReduceThreads, lds, s>>>(rowstart, p.nn, p.rb, icol, ival, rcol, rval, uniq);
+  if (p.nsub > 0) {
+    k_pass3<V><<<(unsigned)p.nsub, 256, 0, s>>>(key2, val2, sbb, p.s2, p.colbits, p.nn, emax, tcol, tval, ucnt, usub);
     KB_LAUNCH_CHECK();
   }
   KB_TRY(ev.rec(KB_STAGE_COMPRESS));
-  KB_TRY(scan(uniq, p.nn, part, row_ptr, nnz_dev, s));
-  if (p.nn > 0) {
-    k_compact<V><<<grid_for(p.nn, 256), 256, 0, s>>>(rowstart, row_ptr, p.nn, rcol, rval, col_idx, vals, cap, status);
+  KB_TRY(scan((const int32_t*)usub, p.nsub, part, (int32_t*)ubase, nnz_dev, s));
+  if (p.nsub > 0) {
+    k_final<V><<<(unsigned)p.nsub, 256, 0, s>>>(sbb, ubase, tcol, tval, ucnt, p.s2, p.nn, p.nsub, row_ptr, col_idx,
+                                                vals, cap, status);
+    KB_LAUNCH_CHECK();
+  } else {
+    k_scan_empty<<<1, 1, 0, s>>>(row_ptr, nullptr);
     KB_LAUNCH_CHECK();
   }
   KB_TRY(ev.rec(KB_N_STAGES));
@@ -165,43 +271,46 @@ int build_impl(const Plan& p, const kb_mesh* m, const void* klow, unsigned char*
                int32_t* col_idx, void* vals, int64_t cap, int64_t* nnz_dev, uint32_t* status, Events& ev,
                hipStream_t s) {
   using V = typename PrecTraits<P>::V;
-  auto* rowcnt = (int32_t*)(ws + p.o_rowcnt);
-  auto* rowstart = (int32_t*)(ws + p.o_rowstart);
-  auto* cursor = (int32_t*)(ws + p.o_cursor);
-  auto* icol = (int32_t*)(ws + p.o_icol);
-  auto* ival = (V*)(ws + p.o_ival);
+  auto* hist = (uint32_t*)(ws + p.o_hist);
+  auto* histT = (uint32_t*)(ws + p.o_histT);
   auto* part = (int32_t*)(ws + p.o_part);
+  auto* total = (int64_t*)(ws + p.o_total);
+  auto* bstart = (uint32_t*)(ws + p.o_bstart);
+  auto* segbase = (uint32_t*)(ws + p.o_segbase);
 
   KB_TRY(ev.rec(KB_STAGE_INIT));
   k_init_status<<<1, 64, 0, s>>>(status, nnz_dev);
   KB_LAUNCH_CHECK();
-  fill(rowcnt, p.nn, 0, s);
-  fill(cursor, p.nn, 0, s);
+  k_fill_i32<<<1, 64, 0, s>>>((int32_t*)(ws + p.o_emax), 1, 0);
   KB_LAUNCH_CHECK();
 
   KB_TRY(ev.rec(KB_STAGE_COUNT));
-  if (p.nel > 0) {
-    k_count<NEN><<<grid_for(p.nel, 256), 256, 0, s>>>(m->conn, p.nel, p.nn, rowcnt, status);
+  if (p.ntiles > 0) {
+    // with no nodes every element has an index error: flagged, nothing counted
+    const int nb = p.nb > 0 ? p.nb : 0;
+    k_hist_buckets<NEN><<<(unsigned)p.ntiles, 256, 4 * (size_t)(nb > 0 ? nb : 1), s>>>(
+        m->conn, p.nel, p.nn, p.tile, nb > 0 ? p.s1 : 30, nb, hist, status);
     KB_LAUNCH_CHECK();
   }
-  KB_TRY(ev.rec(KB_STAGE_SCAN_ROWS));
-  KB_TRY(scan(rowcnt, p.nn, part, rowstart, nullptr, s));
-
+  KB_TRY(ev.rec(KB_STAGE_OFFSETS));
+  if (p.nb > 0) {
+    KB_TRY(transpose(hist, histT, p.ntiles, p.nb, s));  // -> [nb][ntiles]
+    KB_TRY(scan((const int32_t*)histT, p.nhist, part, (int32_t*)histT, total, s));
+    k_bucket_starts<<<grid_for(p.nb + 1, 256), 256, 0, s>>>(histT, p.ntiles, p.nb, total, bstart);
+    KB_LAUNCH_CHECK();
+    KB_TRY(transpose(histT, hist, p.nb, p.ntiles, s));  // -> [ntiles][nb]
+    k_segments<<<1, 256, 0, s>>>(bstart, p.nb, kSeg, segbase);
+    KB_LAUNCH_CHECK();
+  }
   KB_TRY(ev.rec(KB_STAGE_INTEGRATE));
-  if (p.nel > 0) {
-    const unsigned g = grid_for(p.nel, p.block);
-    if (!klow) {
-      // element values into the workspace, then the same scatter as the assembly-only path
-      V* kv = (V*)(ws + p.o_klow);
-      k_integrate_store<NEN, P><<<g, p.block, 0, s>>>(m->conn, m->coords, m->coef, p.nel, p.nn, p.tau, kv, status);
-      KB_LAUNCH_CHECK();
-      klow = kv;
+  if (p.ntiles > 0 && p.nb > 0) {
+    if (klow) {
+      KB_TRY((launch_pass1<NEN, P, true>(p, m, klow, ws, status, s)));
+    } else {
+      KB_TRY((launch_pass1<NEN, P, false>(p, m, nullptr, ws, status, s)));
     }
-    k_scatter_values<NEN, V><<<g, p.block, 0, s>>>(m->conn, (const V*)klow, p.nel, p.nn, rowstart, cursor, icol, ival,
-                                                  status);
-    KB_LAUNCH_CHECK();
   }
-  return reduce_and_compress<V>(p, ws, row_ptr, col_idx, (V*)vals, cap, nnz_dev, status, ev, s);
+  return assemble_tail<V>(p, ws, row_ptr, col_idx, (V*)vals, cap, nnz_dev, status, ev, s);
 }
 
 template <int NEN>
@@ -230,7 +339,7 @@ int integrate_impl(const Plan& p, const kb_mesh* m, void* vals, uint32_t* status
                                                                           p.tau, (V*)vals, status);
     KB_LAUNCH_CHECK();
   }
-  for (int i = KB_STAGE_REDUCE; i <= KB_N_STAGES; ++i) KB_TRY(ev.rec(i));
+  for (int i = KB_STAGE_PARTITION; i <= KB_N_STAGES; ++i) KB_TRY(ev.rec(i));
   return KB_OK;
 }
 

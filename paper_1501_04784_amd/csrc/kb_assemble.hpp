@@ -1,0 +1,634 @@
+// kb_assemble.hpp -- atomic-free assembly of lower-triangular CSR K on gfx950.
+//
+// Every element contributes nen(nen+1)/2 lower pairs (Alg. 1 mapping): the node of
+// rank r in its element (by global id) owns the r+1 pairs (itself, smaller ids) whose
+// global row is that node.  Assembly (Eq. 6) sums the pairs with equal (row, col).
+//
+// Data movement: two partition passes, then a streaming reduction in LDS.
+//   hist     per tile of elements: pairs per row bucket (row >> s1), tile-major.
+//   offsets  transpose + exclusive scan + transpose back: each tile's write offset in
+//            each bucket; bucket boundaries.
+//   pass 1   per tile (one element per lane): integrate the element (or read given
+//            values), stage its pairs in LDS grouped by bucket, write each bucket's run
+//            at the tile's offset as (row, col, value) arrays.  Also the largest value
+//            exponent, which fixes the exact-sum scale below.
+//   pass 2   per fixed-size segment of a bucket: histogram of sub-buckets
+//            (row >> s2), global scan, then LDS-staged scatter into contiguous
+//            sub-bucket ranges; pairs are repacked as (row_local << colbits | col, value).
+//   pass 3   per sub-bucket: stream its pairs into an LDS hash table keyed by the
+//            packed (row, col); each value is added as a 128-bit fixed-point integer
+//            (scale 2^F from the largest exponent), so every sum is exact and its
+//            result does not depend on the order of the additions: the output is
+//            bitwise deterministic although the partition passes order pairs through
+//            LDS atomics.  Entries are then ordered by (row, col) and converted once
+//            (correct rounding of the exact sum to FP64, then to the value type).
+//   final    scan of per-sub-bucket unique counts; row_ptr and the compacted col/vals.
+// A sub-bucket whose distinct entries overflow the table takes a slow single-lane path
+// in global memory (heap sort, then the same exact sums).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kb_element.hpp"
+#include "kb_kernels.hpp"
+#include "kbuild.h"
+
+namespace kb {
+
+constexpr uint32_t kEmptyKey = 0xFFFFFFFFu;  // packed keys never use bit 31
+constexpr int kHT3 = 2048;                   // pass-3 hash slots
+
+// ----------------------------------------------------------------- block helpers
+// exclusive scan of one uint32 per thread across the block; *total = block sum.
+// smem must hold (blockDim/64 + 1) words.  Contains barriers: call from all threads.
+__device__ __forceinline__ uint32_t block_scan_u32(uint32_t v, uint32_t* smem, uint32_t* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint32_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) smem[wave] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t s = 0;
+    for (int w = 0; w < nw; ++w) {
+      uint32_t t = smem[w];
+      smem[w] = s;
+      s += t;
+    }
+    smem[nw] = s;
+  }
+  __syncthreads();
+  const uint32_t r = x - v + smem[wave];
+  *total = smem[nw];
+  __syncthreads();
+  return r;
+}
+
+// in-place exclusive scan of a[0..n) in LDS (n arbitrary); returns the total.
+template <typename T>
+__device__ __forceinline__ uint32_t block_scan_array(T* a, int n, uint32_t* smem) {
+  const int per = (n + (int)blockDim.x - 1) / (int)blockDim.x;
+  const int lo = threadIdx.x * per;
+  uint32_t s = 0;
+  for (int i = 0; i < per; ++i)
+    if (lo + i < n) s += (uint32_t)a[lo + i];
+  uint32_t total;
+  uint32_t off = block_scan_u32(s, smem, &total);
+  for (int i = 0; i < per; ++i)
+    if (lo + i < n) {
+      const uint32_t v = (uint32_t)a[lo + i];
+      a[lo + i] = (T)off;
+      off += v;
+    }
+  __syncthreads();
+  return total;
+}
+
+// ------------------------------------------------------- exact fixed-point sums
+// A finite double v is m * 2^(E-1075) (m < 2^53).  With the scale F = 1117 - Emax,
+// where Emax is the largest biased exponent of all values, q = v * 2^F is below 2^95
+// in magnitude, so up to 2^31 of them sum exactly in a 128-bit two's complement
+// integer.  Bits below 2^-F are dropped (truncation toward zero, independent of
+// order).  Non-finite values contribute 0 (they are flagged elsewhere).
+__device__ __forceinline__ int biased_exponent(double v) {
+  return (int)((__double_as_longlong(v) >> 52) & 0x7FF);
+}
+
+__device__ __forceinline__ void to_fixed(double v, int F, uint64_t& lo, uint64_t& hi) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  int E = (int)((b >> 52) & 0x7FF);
+  uint64_t m = b & ((1ull << 52) - 1);
+  lo = 0;
+  hi = 0;
+  if (E == 0x7FF) return;
+  if (E == 0)
+    E = 1;  // subnormal
+  else
+    m |= 1ull << 52;
+  if (m == 0) return;
+  const int sh = E - 1075 + F;
+  if (sh >= 64) {
+    hi = m << (sh - 64);
+  } else if (sh > 0) {
+    lo = m << sh;
+    hi = m >> (64 - sh);
+  } else if (sh == 0) {
+    lo = m;
+  } else if (sh > -64) {
+    lo = m >> (-sh);
+  }
+  if (b >> 63) {  // negate (two's complement)
+    lo = ~lo + 1;
+    hi = ~hi + (lo == 0 ? 1ull : 0ull);
+  }
+}
+
+// exact 128-bit value -> double, correctly rounded; then scaled by 2^-F
+__device__ __forceinline__ double from_fixed(uint64_t lo, uint64_t hi, int F) {
+  const bool neg = (int64_t)hi < 0;
+  if (neg) {
+    lo = ~lo + 1;
+    hi = ~hi + (lo == 0 ? 1ull : 0ull);
+  }
+  double d;
+  if (hi == 0) {
+    d = (double)lo;
+  } else {
+    const int lz = __clzll((long long)hi);
+    uint64_t top = lz ? ((hi << lz) | (lo >> (64 - lz))) : hi;
+    const uint64_t rest = lz ? (lo << lz) : lo;
+    top |= rest ? 1ull : 0ull;  // sticky bit: 64 > 53 + 2, so rounding stays correct
+    d = ldexp((double)top, 64 - lz);
+  }
+  d = ldexp(d, -F);
+  return neg ? -d : d;
+}
+
+// ---------------------------------------------------------------------- histogram
+// Per tile of `te` elements: pairs per bucket (row >> s1), written tile-major
+// hist[t * nb + b].  Flags index errors; invalid elements contribute nothing.
+template <int NEN>
+__global__ __launch_bounds__(256) void k_hist_buckets(const int32_t* __restrict__ conn, int64_t n_elem, int64_t n_node,
+                                                      int te, int s1, int nb, uint32_t* __restrict__ hist,
+                                                      uint32_t* __restrict__ status) {
+  extern __shared__ uint32_t s_h[];  // [nb]
+  const int64_t t = blockIdx.x;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) s_h[b] = 0;
+  __syncthreads();
+  const int64_t e0 = t * te, e1 = (e0 + te < n_elem) ? e0 + te : n_elem;
+  uint32_t flags = 0;
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    int32_t E[NEN];
+    load_conn<NEN>(conn, e, E);
+    const uint32_t f = check_conn<NEN>(E, n_node);
+    if (f) {
+      flags |= f;
+      continue;
+    }
+    int r[NEN];
+    node_ranks<NEN>(E, r);
+#pragma unroll
+    for (int a = 0; a < NEN; ++a) atomicAdd(&s_h[E[a] >> s1], (uint32_t)(r[a] + 1));
+  }
+  if (flags) raise_flag(status, flags);
+  __syncthreads();
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) hist[t * nb + b] = s_h[b];
+}
+
+// out[c][r] = in[r][c] for an (rows x cols) uint32 matrix
+__global__ __launch_bounds__(256) void k_transpose(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
+                                                   int64_t rows, int64_t cols) {
+  __shared__ uint32_t tile[32][33];
+  const int64_t c0 = (int64_t)blockIdx.x * 32, r0 = (int64_t)blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int k = ty; k < 32; k += 8) {
+    const int64_t r = r0 + k, c = c0 + tx;
+    tile[k][tx] = (r < rows && c < cols) ? in[r * cols + c] : 0u;
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int64_t c = c0 + k, r = r0 + tx;
+    if (c < cols && r < rows) out[c * rows + r] = tile[tx][k];
+  }
+}
+
+// bucket b starts at offT[b * ntiles] (bucket-major scanned histogram); bstart[nb] = total
+__global__ void k_bucket_starts(const uint32_t* __restrict__ offT, int64_t ntiles, int nb, const int64_t* total,
+                                uint32_t* __restrict__ bstart) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < nb) bstart[b] = ntiles > 0 ? offT[(int64_t)b * ntiles] : 0u;
+  if (b == nb) bstart[nb] = (uint32_t)*total;
+}
+
+// single block: segbase[b] = number of pass-2 segments in buckets before b
+// (segbase[nb] = total), a bucket of n pairs having ceil(n / seg) segments
+__global__ __launch_bounds__(256) void k_segments(const uint32_t* __restrict__ bstart, int nb, int seg,
+                                                  uint32_t* __restrict__ segbase) {
+  __shared__ uint32_t s_scan[8];
+  uint32_t carry = 0;
+  for (int b0 = 0; b0 < nb; b0 += blockDim.x) {
+    const int b = b0 + threadIdx.x;
+    const uint32_t n = (b < nb) ? (bstart[b + 1] - bstart[b] + seg - 1) / seg : 0u;
+    uint32_t total;
+    const uint32_t ex = block_scan_u32(n, s_scan, &total);
+    if (b < nb) segbase[b] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0) segbase[nb] = carry;
+}
+
+// ------------------------------------------------------------------------ pass 1
+// Per tile of BLOCK elements (one per lane): produce the element's lower pairs, group
+// them by bucket in LDS, write runs to (orow, ocol, oval).
+template <int NEN, Prec P, bool FROM_VALUES, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_pass1(const int32_t* __restrict__ conn, const double* __restrict__ coords,
+                                               const double* __restrict__ coef,
+                                               const typename PrecTraits<P>::V* __restrict__ klow, int64_t n_elem,
+                                               int64_t n_node, float tau, int s1, int nb,
+                                               const uint32_t* __restrict__ off1, uint32_t* __restrict__ orow,
+                                               uint32_t* __restrict__ ocol, typename PrecTraits<P>::V* __restrict__ oval,
+                                               uint32_t* __restrict__ emax, uint32_t* __restrict__ status) {
+  using V = typename PrecTraits<P>::V;
+  constexpr int T = ElemTraits<NEN>::T;
+  constexpr int CAP = BLOCK * T;
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint64_t* s_key = (uint64_t*)smem;            // [CAP]
+  V* s_val = (V*)(s_key + CAP);                  // [CAP]
+  uint32_t* s_cnt = (uint32_t*)(s_val + CAP);    // [nb]
+  uint32_t* s_base = s_cnt + nb;                 // [nb] global offset of this tile in bucket b
+  uint32_t* s_cur = s_base + nb;                 // [nb] staging cursor
+  uint32_t* s_scan = s_cur + nb;                 // [BLOCK/64 + 1]
+  uint32_t* s_emax = s_scan + (BLOCK / 64 + 1);  // [1]
+
+  const int64_t t = blockIdx.x;
+  for (int b = threadIdx.x; b < nb; b += BLOCK) {
+    s_cnt[b] = 0;
+    s_base[b] = off1[t * nb + b];
+  }
+  if (threadIdx.x == 0) *s_emax = 0;
+  __syncthreads();
+  const int64_t e = t * BLOCK + threadIdx.x;
+  int32_t E[NEN];
+  bool valid = false;
+  if (e < n_elem) {
+    load_conn<NEN>(conn, e, E);
+    valid = check_conn<NEN>(E, n_node) == 0;
+  }
+  int r[NEN];
+  if (valid) {
+    node_ranks<NEN>(E, r);
+#pragma unroll
+    for (int a = 0; a < NEN; ++a) atomicAdd(&s_cnt[E[a] >> s1], (uint32_t)(r[a] + 1));
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < nb; b += BLOCK) s_cur[b] = s_cnt[b];
+  __syncthreads();
+  const uint32_t n_items = block_scan_array(s_cur, nb, s_scan);  // s_cur = local starts
+  for (int b = threadIdx.x; b < nb; b += BLOCK) s_cnt[b] = s_cur[b];  // s_cnt = local starts (kept)
+  __syncthreads();
+  uint32_t flags = 0, fb = 0;
+  if (valid) {
+    V k[T];
+    if constexpr (FROM_VALUES) {
+      bool finite = true;
+#pragma unroll
+      for (int p = 0; p < T; ++p) {
+        k[p] = klow[e * T + p];
+        finite = finite && isfinite((double)k[p]);
+      }
+      if (!finite) flags |= KB_F_NONFINITE;
+    } else {
+      element_values<NEN, P>(coords, coef, e, E, tau, k, &flags, &fb);
+    }
+    int em = 0;
+#pragma unroll
+    for (int p = 0; p < T; ++p) {
+      const int ep = biased_exponent((double)k[p]);
+      em = (ep > em && ep < 0x7FF) ? ep : em;
+    }
+    atomicMax(s_emax, (uint32_t)em);
+#pragma unroll
+    for (int a = 0; a < NEN; ++a) {
+      // the r+1 pairs of row E[a] are staged contiguously
+      uint32_t pos = atomicAdd(&s_cur[E[a] >> s1], (uint32_t)(r[a] + 1));
+      const uint64_t hi = (uint64_t)(uint32_t)E[a] << 32;
+#pragma unroll
+      for (int b = 0; b < NEN; ++b) {
+        if (E[b] <= E[a]) {
+          s_key[pos] = hi | (uint32_t)E[b];
+          s_val[pos] = (a >= b) ? k[lidx(a, b)] : k[lidx(b, a)];
+          ++pos;
+        }
+      }
+    }
+  }
+  if (flags) raise_flag(status, flags);
+  if (fb) atomicAdd(&status[1], fb);
+  __syncthreads();
+  if (threadIdx.x == 0 && *s_emax) atomicMax(emax, *s_emax);
+  // write runs: staged index i lies in bucket b = row >> s1, local start s_cnt[b]
+  for (uint32_t i = threadIdx.x; i < n_items; i += BLOCK) {
+    const uint64_t key = s_key[i];
+    const uint32_t row = (uint32_t)(key >> 32);
+    const int b = (int)(row >> s1);
+    const uint32_t g = s_base[b] + (i - s_cnt[b]);
+    orow[g] = row;
+    ocol[g] = (uint32_t)key;
+    oval[g] = s_val[i];
+  }
+}
+
+// ------------------------------------------------------------------------ pass 2
+// Segment id -> (bucket b, index s within b); false past the last segment.
+__device__ __forceinline__ bool find_segment(int64_t sid, const uint32_t* segbase, int nb, int& b, uint32_t& s) {
+  if (sid >= (int64_t)segbase[nb]) return false;
+  int lo = 0, hi = nb - 1;  // largest b with segbase[b] <= sid
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if ((int64_t)segbase[mid] <= sid)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  b = lo;
+  s = (uint32_t)(sid - segbase[lo]);
+  return true;
+}
+
+// histogram of sub-buckets per segment: hist2[segbase[b] * p2 + j * nseg_b + s], an
+// order whose exclusive scan is the position of each (segment, sub-bucket) run
+template <int SEG>
+__global__ __launch_bounds__(256) void k_hist2(const uint32_t* __restrict__ irow, const uint32_t* __restrict__ bstart,
+                                               const uint32_t* __restrict__ segbase, int nb, int s2, int p2,
+                                               uint32_t* __restrict__ hist2) {
+  extern __shared__ uint32_t s_h[];  // [p2]
+  int b;
+  uint32_t s;
+  if (!find_segment(blockIdx.x, segbase, nb, b, s)) return;
+  for (int j = threadIdx.x; j < p2; j += blockDim.x) s_h[j] = 0;
+  __syncthreads();
+  const uint32_t bs = bstart[b], be = bstart[b + 1];
+  const uint32_t i0 = bs + s * SEG, i1 = (i0 + SEG < be) ? i0 + SEG : be;
+  const uint32_t mask = (uint32_t)p2 - 1;
+  for (uint32_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) atomicAdd(&s_h[(irow[i] >> s2) & mask], 1u);
+  __syncthreads();
+  const uint32_t nseg = segbase[b + 1] - segbase[b];
+  const int64_t base = (int64_t)segbase[b] * p2 + s;
+  for (int j = threadIdx.x; j < p2; j += blockDim.x) hist2[base + (int64_t)j * nseg] = s_h[j];
+}
+
+// first pair of each sub-bucket: sbb[b * p2 + j]; sbb[nb * p2] = total
+__global__ void k_subbucket_starts(const uint32_t* __restrict__ off2, const uint32_t* __restrict__ bstart,
+                                   const uint32_t* __restrict__ segbase, int nb, int p2, uint32_t* __restrict__ sbb) {
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t nsub = (int64_t)nb * p2;
+  if (g > nsub) return;
+  if (g == nsub) {
+    sbb[nsub] = bstart[nb];
+    return;
+  }
+  const int b = (int)(g / p2), j = (int)(g % p2);
+  const uint32_t nseg = segbase[b + 1] - segbase[b];
+  sbb[g] = nseg ? off2[(int64_t)segbase[b] * p2 + (int64_t)j * nseg] : bstart[b];
+}
+
+// scatter a segment into its sub-buckets; output key = row_local << colbits | col
+template <typename V, int SEG>
+__global__ __launch_bounds__(256) void k_scatter2(const uint32_t* __restrict__ irow, const uint32_t* __restrict__ icol,
+                                                  const V* __restrict__ ival, const uint32_t* __restrict__ bstart,
+                                                  const uint32_t* __restrict__ segbase,
+                                                  const uint32_t* __restrict__ off2, int nb, int s2, int p2,
+                                                  int colbits, uint32_t* __restrict__ okey, V* __restrict__ oval) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  V* s_val = (V*)smem;                          // [SEG]
+  uint32_t* s_key = (uint32_t*)(s_val + SEG);   // [SEG]
+  uint16_t* s_sb = (uint16_t*)(s_key + SEG);    // [SEG] sub-bucket of staged pair
+  uint32_t* s_cnt = (uint32_t*)(s_sb + SEG);    // [p2] local starts
+  uint32_t* s_cur = s_cnt + p2;                 // [p2]
+  uint32_t* s_off = s_cur + p2;                 // [p2] global offsets
+  uint32_t* s_scan = s_off + p2;                // [5]
+  int b;
+  uint32_t s;
+  if (!find_segment(blockIdx.x, segbase, nb, b, s)) return;
+  const uint32_t nseg = segbase[b + 1] - segbase[b];
+  const int64_t hbase = (int64_t)segbase[b] * p2 + s;
+  for (int j = threadIdx.x; j < p2; j += blockDim.x) {
+    s_cnt[j] = 0;
+    s_off[j] = off2[hbase + (int64_t)j * nseg];
+  }
+  __syncthreads();
+  const uint32_t bs = bstart[b], be = bstart[b + 1];
+  const uint32_t i0 = bs + s * SEG, i1 = (i0 + SEG < be) ? i0 + SEG : be;
+  const uint32_t mask = (uint32_t)p2 - 1, rmask = (1u << s2) - 1;
+  constexpr int PER = SEG / 256;
+  uint32_t rr[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const uint32_t i = i0 + q * 256 + threadIdx.x;
+    if (i < i1) {
+      rr[q] = irow[i];
+      atomicAdd(&s_cnt[(rr[q] >> s2) & mask], 1u);
+    }
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < p2; j += blockDim.x) s_cur[j] = s_cnt[j];
+  __syncthreads();
+  block_scan_array(s_cur, p2, s_scan);
+  for (int j = threadIdx.x; j < p2; j += blockDim.x) s_cnt[j] = s_cur[j];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const uint32_t i = i0 + q * 256 + threadIdx.x;
+    if (i < i1) {
+      const uint32_t j = (rr[q] >> s2) & mask;
+      const uint32_t pos = atomicAdd(&s_cur[j], 1u);
+      s_key[pos] = ((rr[q] & rmask) << colbits) | icol[i];
+      s_val[pos] = ival[i];
+      s_sb[pos] = (uint16_t)j;
+    }
+  }
+  __syncthreads();
+  const uint32_t n = i1 - i0;
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const uint32_t j = s_sb[i];
+    const uint32_t g = s_off[j] + (i - s_cnt[j]);
+    okey[g] = s_key[i];
+    oval[g] = s_val[i];
+  }
+}
+
+// ------------------------------------------------------------------------ pass 3
+__device__ __forceinline__ uint32_t key_hash(uint32_t k) {
+  k ^= k >> 16;
+  k *= 0x7FEB352Du;
+  k ^= k >> 15;
+  k *= 0x846CA68Bu;
+  k ^= k >> 16;
+  return k;
+}
+
+// single-lane path for a sub-bucket whose distinct entries overflow the table: heap
+// sort the pairs in place by key, then exact sums of equal keys (same result as the
+// LDS path, which uses the same exact arithmetic).
+template <typename V>
+__device__ void pass3_global(uint32_t* key, V* val, int64_t n, int64_t r0, int R, int colbits, int F, int32_t* tcol,
+                             V* tval, int32_t* ucnt, uint32_t* usub) {
+  auto sift = [&](int64_t root, int64_t end) {
+    while (true) {
+      int64_t child = 2 * root + 1;
+      if (child >= end) break;
+      if (child + 1 < end && key[child] < key[child + 1]) ++child;
+      if (!(key[root] < key[child])) break;
+      const uint32_t tk = key[root];
+      key[root] = key[child];
+      key[child] = tk;
+      const V tv = val[root];
+      val[root] = val[child];
+      val[child] = tv;
+      root = child;
+    }
+  };
+  for (int64_t s = n / 2 - 1; s >= 0; --s) sift(s, n);
+  for (int64_t end = n - 1; end > 0; --end) {
+    const uint32_t tk = key[0];
+    key[0] = key[end];
+    key[end] = tk;
+    const V tv = val[0];
+    val[0] = val[end];
+    val[end] = tv;
+    sift(0, end);
+  }
+  for (int r = 0; r < R; ++r) ucnt[r0 + r] = 0;
+  const uint32_t cmask = (1u << colbits) - 1;
+  int64_t u = 0, q = 0;
+  while (q < n) {
+    const uint32_t k0 = key[q];
+    uint64_t lo = 0, hi = 0;
+    while (q < n && key[q] == k0) {
+      uint64_t a, b;
+      to_fixed((double)val[q], F, a, b);
+      const uint64_t s = lo + a;
+      hi += b + (s < lo ? 1ull : 0ull);
+      lo = s;
+      ++q;
+    }
+    tcol[u] = (int32_t)(k0 & cmask);
+    tval[u] = (V)from_fixed(lo, hi, F);
+    ucnt[r0 + (k0 >> colbits)] += 1;
+    ++u;
+  }
+  *usub = (uint32_t)u;
+}
+
+// One workgroup per sub-bucket g (rows [g << s2, ...)).  Writes its unique entries in
+// CSR order to tcol/tval[sbb[g] + f], per-row unique counts to ucnt, total to usub[g].
+template <typename V>
+__global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* __restrict__ ival,
+                                               const uint32_t* __restrict__ sbb, int s2, int colbits, int64_t n_node,
+                                               const uint32_t* __restrict__ emax, int32_t* __restrict__ tcol,
+                                               V* __restrict__ tval, int32_t* __restrict__ ucnt,
+                                               uint32_t* __restrict__ usub) {
+  constexpr int HT = kHT3;
+  __shared__ uint32_t s_key[HT];
+  __shared__ unsigned long long s_lo[HT];
+  __shared__ unsigned long long s_hi[HT];
+  __shared__ uint16_t s_w[HT];     // index of the slot within its row
+  __shared__ uint16_t s_list[HT];  // slots grouped by row
+  __shared__ uint32_t s_rc[256];   // entries per row
+  __shared__ uint32_t s_ro[256];   // row offsets
+  __shared__ uint32_t s_scan[8];
+  __shared__ uint32_t s_over;
+
+  const int64_t g = blockIdx.x;
+  const uint32_t beg = sbb[g], end = sbb[g + 1];
+  const int64_t r0 = g << s2;
+  const int64_t rr = n_node - r0;
+  const int R = rr <= 0 ? 0 : (rr < ((int64_t)1 << s2) ? (int)rr : (1 << s2));
+  const int F = 1117 - (int)*emax;
+  const uint32_t cmask = (1u << colbits) - 1;
+
+  for (int h = threadIdx.x; h < HT; h += blockDim.x) {
+    s_key[h] = kEmptyKey;
+    s_lo[h] = 0ull;
+    s_hi[h] = 0ull;
+  }
+  for (int r = threadIdx.x; r < 256; r += blockDim.x) s_rc[r] = 0;
+  if (threadIdx.x == 0) s_over = 0;
+  __syncthreads();
+  // stream the pairs into the table
+  for (uint32_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
+    const uint32_t key = ikey[i];
+    uint64_t qlo, qhi;
+    to_fixed((double)ival[i], F, qlo, qhi);
+    uint32_t h = key_hash(key) & (HT - 1);
+    int probes = 0;
+    bool found = false;
+    while (probes < HT) {
+      uint32_t k = s_key[h];
+      if (k == kEmptyKey) k = atomicCAS(&s_key[h], kEmptyKey, key);
+      if (k == kEmptyKey || k == key) {
+        found = true;
+        break;
+      }
+      h = (h + 1) & (HT - 1);
+      ++probes;
+    }
+    if (!found) {
+      s_over = 1;
+      break;
+    }
+    const unsigned long long old = atomicAdd(&s_lo[h], (unsigned long long)qlo);
+    const uint64_t carry = (old + qlo < old) ? 1ull : 0ull;
+    const uint64_t add_hi = qhi + carry;
+    if (add_hi) atomicAdd(&s_hi[h], (unsigned long long)add_hi);
+  }
+  __syncthreads();
+  if (s_over) {
+    if (threadIdx.x == 0)
+      pass3_global<V>(ikey + beg, ival + beg, end - beg, r0, R, colbits, F, tcol + beg, tval + beg, ucnt, usub + g);
+    return;
+  }
+  // order the entries by (row, col)
+  for (int h = threadIdx.x; h < HT; h += blockDim.x) {
+    const uint32_t k = s_key[h];
+    if (k != kEmptyKey) s_w[h] = (uint16_t)atomicAdd(&s_rc[k >> colbits], 1u);
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < 256; r += blockDim.x) s_ro[r] = s_rc[r];
+  __syncthreads();
+  const uint32_t U = block_scan_array(s_ro, 256, s_scan);
+  for (int h = threadIdx.x; h < HT; h += blockDim.x) {
+    const uint32_t k = s_key[h];
+    if (k != kEmptyKey) s_list[s_ro[k >> colbits] + s_w[h]] = (uint16_t)h;
+  }
+  __syncthreads();
+  for (int h = threadIdx.x; h < HT; h += blockDim.x) {
+    const uint32_t k = s_key[h];
+    if (k == kEmptyKey) continue;
+    const uint32_t row = k >> colbits, col = k & cmask;
+    const uint32_t ro = s_ro[row], nr = s_rc[row];
+    uint32_t rank = 0;
+    for (uint32_t q = 0; q < nr; ++q) rank += ((s_key[s_list[ro + q]] & cmask) < col) ? 1u : 0u;
+    const uint32_t f = ro + rank;
+    tcol[beg + f] = (int32_t)col;
+    tval[beg + f] = (V)from_fixed(s_lo[h], s_hi[h], F);
+  }
+  for (int r = threadIdx.x; r < R; r += blockDim.x) ucnt[r0 + r] = (int32_t)s_rc[r];
+  if (threadIdx.x == 0) usub[g] = U;
+}
+
+// ------------------------------------------------------------------------- final
+// Per sub-bucket: compacted col/vals at ubase[g], row_ptr of its rows.
+template <typename V>
+__global__ __launch_bounds__(256) void k_final(const uint32_t* __restrict__ sbb, const uint32_t* __restrict__ ubase,
+                                               const int32_t* __restrict__ tcol, const V* __restrict__ tval,
+                                               const int32_t* __restrict__ ucnt, int s2, int64_t n_node, int64_t nsub,
+                                               int32_t* __restrict__ row_ptr, int32_t* __restrict__ col_idx,
+                                               V* __restrict__ vals, int64_t cap, uint32_t* __restrict__ status) {
+  __shared__ uint32_t s_r[256];
+  __shared__ uint32_t s_scan[8];
+  const int64_t g = blockIdx.x;
+  const int64_t nnz = ubase[nsub];
+  const uint32_t base = ubase[g], U = ubase[g + 1] - ubase[g];
+  const int64_t r0 = g << s2, rr = n_node - r0;
+  const int R = rr <= 0 ? 0 : (rr < ((int64_t)1 << s2) ? (int)rr : (1 << s2));
+  if (nnz <= cap) {
+    const uint32_t src = sbb[g];
+    for (uint32_t f = threadIdx.x; f < U; f += blockDim.x) {
+      col_idx[base + f] = tcol[src + f];
+      vals[base + f] = tval[src + f];
+    }
+  } else if (g == 0 && threadIdx.x == 0) {
+    raise_flag(status, KB_F_CAPACITY);
+  }
+  for (int r = threadIdx.x; r < 256; r += blockDim.x) s_r[r] = (r < R) ? (uint32_t)ucnt[r0 + r] : 0u;
+  __syncthreads();
+  block_scan_array(s_r, 256, s_scan);
+  for (int r = threadIdx.x; r < R; r += blockDim.x) row_ptr[r0 + r] = (int32_t)(base + s_r[r]);
+  if (g == nsub - 1 && threadIdx.x == 0) row_ptr[n_node] = (int32_t)nnz;
+}
+
+}  // namespace kb

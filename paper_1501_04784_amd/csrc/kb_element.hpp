@@ -129,6 +129,8 @@ __device__ __forceinline__ bool hex_integrate(const GT (&X)[8][3], AT (&k)[36], 
 #pragma unroll
       for (int b = 0; b <= a; ++b) k[lidx(a, b)] += g0 * G[0][b] + g1 * G[1][b] + g2 * G[2][b];
     }
+    // keep the eight points in sequence: interleaving them only raises register pressure
+    __builtin_amdgcn_sched_barrier(0);
   }
   return ok;
 }

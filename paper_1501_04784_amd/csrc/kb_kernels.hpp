@@ -1,18 +1,8 @@
 // kb_kernels.hpp -- gfx950 kernels of the lower-triangular stiffness build.
 //
-// Pipeline (each stage one launch, all on the caller's stream):
-//   count      one lane per element: validate ids, rank the element's nodes by global
-//              id; the node of rank r owns r+1 lower pairs (itself and the r smaller
-//              ids), so rowcnt[node] += r+1.
-//   scan       exclusive scan of rowcnt -> rowstart (row segments of the triplet list).
-//   integrate  one lane per element (Alg. 2): integrate the lower triangle of k_e
-//              into element-major storage;
-//   scatter    one lane per element: write each lower pair (col, value) into the
-//              segment of its row, row = max(E_a, E_b) (Alg. 1 mapping).
-//   reduce     per block of rows: order each row's entries by (col, value bits) -- a
-//              canonical order, so sums do not depend on the scatter order -- and sum
-//              equal columns in FP64 (Eq. 6).
-//   compress   scan of the per-row unique counts -> row_ptr, nnz; copy col / vals.
+// Shared pieces: connectivity checks, node ranks, device-wide int32 scan, the
+// per-element integration wrapper (precision modes, FP64 fallback, flags) and the
+// element-major integration kernel.  The assembly kernels are in kb_assemble.hpp.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -25,8 +15,6 @@ namespace kb {
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanChunk = kScanThreads * kScanItems;
-constexpr int kReduceThreads = 256;
-constexpr int kReduceCap = 4096;  // entries of one row block held in LDS
 
 __device__ __forceinline__ void raise_flag(uint32_t* status, uint32_t f) { atomicOr(status, f); }
 
@@ -72,25 +60,6 @@ __global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
 __global__ void k_init_status(uint32_t* __restrict__ status, int64_t* __restrict__ nnz) {
   if (threadIdx.x < KB_STATUS_WORDS) status[threadIdx.x] = 0u;
   if (threadIdx.x == 0 && nnz) *nnz = 0;
-}
-
-// ------------------------------------------------------------------------ count
-template <int NEN>
-__global__ __launch_bounds__(256) void k_count(const int32_t* __restrict__ conn, int64_t n_elem, int64_t n_node,
-                                               int32_t* __restrict__ rowcnt, uint32_t* __restrict__ status) {
-  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= n_elem) return;
-  int32_t E[NEN];
-  load_conn<NEN>(conn, e, E);
-  const uint32_t f = check_conn<NEN>(E, n_node);
-  if (f) {
-    raise_flag(status, f);
-    return;
-  }
-  int r[NEN];
-  node_ranks<NEN>(E, r);
-#pragma unroll
-  for (int a = 0; a < NEN; ++a) atomicAdd(&rowcnt[E[a]], r[a] + 1);
 }
 
 // --------------------------------------------------------------------- scan (int32)
@@ -191,7 +160,7 @@ __global__ void k_scan_empty(int32_t* __restrict__ out, int64_t* __restrict__ to
   if (total64) *total64 = 0;
 }
 
-// ------------------------------------------------------------ integrate (+ scatter)
+// --------------------------------------------------------------------- integrate
 enum class Prec { F64, F32, F32FB };
 
 template <Prec P>
@@ -293,51 +262,6 @@ __global__ __launch_bounds__(256) void k_integrate_store(const int32_t* __restri
   if (fb) atomicAdd(&status[1], fb);
 }
 
-// write the lower pairs of one element into the row segments
-template <int NEN, typename V>
-__device__ __forceinline__ void scatter_element(const int32_t (&E)[NEN], const V (&k)[ElemTraits<NEN>::T],
-                                                const int32_t* __restrict__ rowstart, int32_t* __restrict__ cursor,
-                                                int32_t* __restrict__ icol, V* __restrict__ ival) {
-  int r[NEN];
-  node_ranks<NEN>(E, r);
-#pragma unroll
-  for (int a = 0; a < NEN; ++a) {
-    const int32_t base = rowstart[E[a]] + atomicAdd(&cursor[E[a]], r[a] + 1);
-    int j = 0;
-#pragma unroll
-    for (int b = 0; b < NEN; ++b) {
-      if (E[b] <= E[a]) {
-        icol[base + j] = E[b];
-        ival[base + j] = (a >= b) ? k[lidx(a, b)] : k[lidx(b, a)];
-        ++j;
-      }
-    }
-  }
-}
-
-template <int NEN, typename V>
-__global__ __launch_bounds__(256) void k_scatter_values(const int32_t* __restrict__ conn, const V* __restrict__ klow,
-                                                        int64_t n_elem, int64_t n_node,
-                                                        const int32_t* __restrict__ rowstart,
-                                                        int32_t* __restrict__ cursor, int32_t* __restrict__ icol,
-                                                        V* __restrict__ ival, uint32_t* __restrict__ status) {
-  constexpr int T = ElemTraits<NEN>::T;
-  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= n_elem) return;
-  int32_t E[NEN];
-  load_conn<NEN>(conn, e, E);
-  if (check_conn<NEN>(E, n_node)) return;
-  V k[T];
-  bool finite = true;
-#pragma unroll
-  for (int p = 0; p < T; ++p) {
-    k[p] = klow[e * T + p];
-    finite = finite && isfinite((double)k[p]);
-  }
-  scatter_element<NEN, V>(E, k, rowstart, cursor, icol, ival);
-  if (!finite) raise_flag(status, KB_F_NONFINITE);
-}
-
 // ------------------------------------------------------------------- row reduce
 template <typename V>
 struct Bits;
@@ -351,151 +275,5 @@ struct Bits<float> {
   using U = uint32_t;
   __device__ static U get(float v) { return __float_as_uint(v); }
 };
-
-template <typename V>
-__device__ __forceinline__ bool entry_less(int32_t ca, typename Bits<V>::U ba, int ia, int32_t cb,
-                                           typename Bits<V>::U bb, int ib) {
-  return ca < cb || (ca == cb && (ba < bb || (ba == bb && ia < ib)));
-}
-
-// single-lane heap sort of (col, val) by (col, value bits), for oversized row blocks
-template <typename V>
-__device__ void heap_sort_entries(int32_t* col, V* val, int64_t n) {
-  auto less = [&](int64_t x, int64_t y) {
-    typename Bits<V>::U bx = Bits<V>::get(val[x]), by = Bits<V>::get(val[y]);
-    return col[x] < col[y] || (col[x] == col[y] && bx < by);
-  };
-  auto swap = [&](int64_t x, int64_t y) {
-    int32_t tc = col[x];
-    col[x] = col[y];
-    col[y] = tc;
-    V tv = val[x];
-    val[x] = val[y];
-    val[y] = tv;
-  };
-  auto sift = [&](int64_t root, int64_t end) {
-    while (true) {
-      int64_t child = 2 * root + 1;
-      if (child >= end) break;
-      if (child + 1 < end && less(child, child + 1)) ++child;
-      if (!less(root, child)) break;
-      swap(root, child);
-      root = child;
-    }
-  };
-  for (int64_t s = n / 2 - 1; s >= 0; --s) sift(s, n);
-  for (int64_t end = n - 1; end > 0; --end) {
-    swap(0, end);
-    sift(0, end);
-  }
-}
-
-// Rows [r0, r0 + rb): reduced entries go to rcol / rval at rowstart[row] + u,
-// uniq[row] = number of distinct columns.
-template <typename V>
-__global__ __launch_bounds__(kReduceThreads) void k_row_reduce(const int32_t* __restrict__ rowstart, int64_t n_node,
-                                                               int rb, const int32_t* __restrict__ icol,
-                                                               const V* __restrict__ ival, int32_t* __restrict__ rcol,
-                                                               V* __restrict__ rval, int32_t* __restrict__ uniq) {
-  using U = typename Bits<V>::U;
-  extern __shared__ __align__(16) unsigned char smem[];
-  V* s_val = (V*)smem;                                   // [kReduceCap]
-  int32_t* s_col = (int32_t*)(s_val + kReduceCap);       // [kReduceCap]
-  uint16_t* s_perm = (uint16_t*)(s_col + kReduceCap);    // [kReduceCap]
-  int32_t* s_rs = (int32_t*)(s_perm + kReduceCap);       // [rb + 1]
-
-  const int64_t r0 = (int64_t)blockIdx.x * rb;
-  const int nr = (int)((n_node - r0) < rb ? (n_node - r0) : rb);
-  const int32_t base = rowstart[r0];
-  const int32_t n = rowstart[r0 + nr] - base;
-  if (n <= kReduceCap) {
-    for (int i = threadIdx.x; i <= nr; i += blockDim.x) s_rs[i] = rowstart[r0 + i] - base;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      s_col[i] = icol[base + i];
-      s_val[i] = ival[base + i];
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      int lo = 0, hi = nr - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (s_rs[mid] <= i)
-          lo = mid;
-        else
-          hi = mid - 1;
-      }
-      const int rs = s_rs[lo], re = s_rs[lo + 1];
-      const int32_t c = s_col[i];
-      const U b = Bits<V>::get(s_val[i]);
-      int rank = 0;
-      for (int j = rs; j < re; ++j) rank += entry_less<V>(s_col[j], Bits<V>::get(s_val[j]), j, c, b, i) ? 1 : 0;
-      s_perm[rs + rank] = (uint16_t)i;
-    }
-    __syncthreads();
-    for (int r = threadIdx.x; r < nr; r += blockDim.x) {
-      const int rs = s_rs[r], re = s_rs[r + 1];
-      const int32_t out = base + rs;
-      int u = 0, q = rs;
-      while (q < re) {
-        const int i0 = s_perm[q];
-        const int32_t c = s_col[i0];
-        double acc = (double)s_val[i0];
-        ++q;
-        while (q < re && s_col[s_perm[q]] == c) {
-          acc += (double)s_val[s_perm[q]];
-          ++q;
-        }
-        rcol[out + u] = c;
-        rval[out + u] = (V)acc;
-        ++u;
-      }
-      uniq[r0 + r] = u;
-    }
-  } else {
-    // oversized block: one lane per row, in global memory
-    for (int r = threadIdx.x; r < nr; r += blockDim.x) {
-      const int64_t rs = rowstart[r0 + r], re = rowstart[r0 + r + 1];
-      for (int64_t i = rs; i < re; ++i) {
-        rcol[i] = icol[i];
-        rval[i] = ival[i];
-      }
-      heap_sort_entries<V>(rcol + rs, rval + rs, re - rs);
-      int64_t u = 0, q = rs;
-      while (q < re) {
-        const int32_t c = rcol[q];
-        double acc = (double)rval[q];
-        ++q;
-        while (q < re && rcol[q] == c) {
-          acc += (double)rval[q];
-          ++q;
-        }
-        rcol[rs + u] = c;
-        rval[rs + u] = (V)acc;
-        ++u;
-      }
-      uniq[r0 + r] = (int32_t)u;
-    }
-  }
-}
-
-// ----------------------------------------------------------------------- compact
-template <typename V>
-__global__ __launch_bounds__(256) void k_compact(const int32_t* __restrict__ rowstart, const int32_t* __restrict__ row_ptr,
-                                                 int64_t n_node, const int32_t* __restrict__ rcol,
-                                                 const V* __restrict__ rval, int32_t* __restrict__ col_idx,
-                                                 V* __restrict__ vals, int64_t cap, uint32_t* __restrict__ status) {
-  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int64_t nnz = row_ptr[n_node];
-  if (nnz > cap) {
-    if (r == 0) raise_flag(status, KB_F_CAPACITY);
-    return;
-  }
-  if (r >= n_node) return;
-  const int64_t src = rowstart[r], dst = row_ptr[r], n = row_ptr[r + 1] - row_ptr[r];
-  for (int64_t i = 0; i < n; ++i) {
-    col_idx[dst + i] = rcol[src + i];
-    vals[dst + i] = rval[src + i];
-  }
-}
 
 }  // namespace kb

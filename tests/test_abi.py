@@ -67,8 +67,8 @@ def test_plan_sizes(elem, te, prec):
     rc, ws, nt = _plan(elem, 1000, 1331, prec)
     assert rc == 0 and nt == 1000 * te
     vb = 8 if prec == 0 else 4
-    # at least: element values, two (col, value) lists, four per-node int arrays
-    assert ws >= nt * (vb + 2 * (4 + vb)) + 4 * 4 * 1331
+    # at least: (row, col, value) and (packed key, value) pair lists, per-node unique counts
+    assert ws >= nt * (12 + 2 * vb) + 4 * 1331
     assert ws % 256 == 0
 
 
@@ -88,10 +88,12 @@ def test_plan_errors():
     assert _plan(4, 10, 2**31)[0] == _lib.KB_ERANGE
     assert _plan(4, 2**31 // 10, 10)[0] == 0
     assert _plan(8, 10, 10, tuning=KbTuning(100, 0, 0.0, 0, None))[0] == _lib.KB_EINVAL  # block not multiple of 64
-    assert _plan(8, 10, 10, tuning=KbTuning(0, 3, 0.0, 0, None))[0] == _lib.KB_EINVAL  # not a power of two
+    assert _plan(8, 10, 10, tuning=KbTuning(0, 31, 0.0, 0, None))[0] == _lib.KB_EINVAL  # bucket bits
     assert _plan(8, 10, 10, tuning=KbTuning(0, 0, 0.5, 0, None))[0] == _lib.KB_EINVAL  # tau <= 1
-    assert _plan(8, 10, 10, tuning=KbTuning(0, 0, 0.0, 1, None))[0] == _lib.KB_EINVAL  # reserved
-    assert _plan(8, 10, 10, tuning=KbTuning(512, 64, 8.0, 0, None))[0] == 0
+    assert _plan(8, 10, 10, tuning=KbTuning(0, 0, 0.0, 9, None))[0] == _lib.KB_EINVAL  # sub-bucket bits > 8
+    assert _plan(8, 10, 10, tuning=KbTuning(0, 3, 0.0, 5, None))[0] == _lib.KB_EINVAL  # sub > bucket
+    assert _plan(8, 10, 10, tuning=KbTuning(0, 20, 0.0, 2, None))[0] == _lib.KB_EINVAL  # > 4096 sub-buckets
+    assert _plan(8, 10, 10, tuning=KbTuning(512, 10, 8.0, 4, None))[0] == 0
 
 
 def test_build_argument_errors_return_before_any_launch():
