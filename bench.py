@@ -71,12 +71,15 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sample", type=int, default=10_000_000, help="elements in the oracle's timed sample")
     ap.add_argument("--profile-steps", action="store_true", help="no stage events (for profiler runs)")
+    ap.add_argument("--block", type=int, default=0, help="tuning: element tile / block size")
+    ap.add_argument("--bucket-bits", type=int, default=0, help="tuning: log2 rows per first-level bucket")
+    ap.add_argument("--sub-bits", type=int, default=0, help="tuning: log2 rows per sub-bucket")
     return ap.parse_args()
 
 
-def time_builds(kb, torch, mesh_dev, m, prec, steps, warmup, stage_events=True):
+def time_builds(kb, torch, mesh_dev, m, prec, steps, warmup, stage_events=True, tuning=None):
     conn, coords, coef = mesh_dev
-    b = kb.Builder(m.elem, m.n_elem, m.n_node, prec=prec)
+    b = kb.Builder(m.elem, m.n_elem, m.n_node, prec=prec, tuning=tuning)
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
         b.run(conn, coords, coef)
@@ -143,8 +146,9 @@ def main():
     torch.cuda.synchronize()
     print(f"[bench] {m.n_elem} elements, {m.n_node} nodes on device; timing {prec}", file=sys.stderr, flush=True)
 
+    tuning = kb.Tuning(block=args.block, bucket_bits=args.bucket_bits, sub_bits=args.sub_bits)
     ms, wall_ms, stages, res = time_builds(kb, torch, mesh_dev, m, prec, args.steps, args.warmup,
-                                           stage_events=not args.profile_steps)
+                                           stage_events=not args.profile_steps, tuning=tuning)
     nnz = res.nnz
     print(f"[bench] {prec}: {ms:.3f} ms/step, nnz {nnz}, fallback elements {res.n_fallback}", file=sys.stderr,
           flush=True)
@@ -155,7 +159,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if prec == "fp64" else "f32", "data": "synthetic",
         "config": {"workload": desc, "n_elem": m.n_elem, "n_node": m.n_node, "nnz": nnz, "precision": prec,
-                   "fp64_fallback_elements": res.n_fallback, "parallelism": "single GPU"},
+                   "fp64_fallback_elements": res.n_fallback, "parallelism": "single GPU",
+                   "tuning": {"block": args.block, "bucket_bits": args.bucket_bits, "sub_bits": args.sub_bits}},
         "path_hbm_frac": ab["path"] / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
     }
     if stages:
@@ -166,7 +171,8 @@ def main():
         out["stages_ms"] = stages
     if not args.no_fp64 and prec != "fp64":
         ms64, _, st64, r64 = time_builds(kb, torch, mesh_dev, m, "fp64", max(3, args.steps // 2), 2,
-                                         stage_events=False)
+                                         stage_events=False, tuning=kb.Tuning(bucket_bits=args.bucket_bits,
+                                                                              sub_bits=args.sub_bits))
         out["fp64"] = {"ms_per_step": ms64, "value": m.n_elem / (ms64 * 1e-3)}
         out["speedup_vs_fp64"] = ms64 / ms
         print(f"[bench] fp64: {ms64:.3f} ms/step", file=sys.stderr, flush=True)

@@ -21,6 +21,8 @@ constexpr float kDefaultTau = 16.0f;
 constexpr int kDefaultBlock = 256;
 constexpr int kSeg = 4096;         // pairs per pass-2 segment
 constexpr int kTargetBuckets = 512;  // first-level buckets (pass-1 run length)
+constexpr double kSubEntries = 300;   // target distinct entries per sub-bucket
+constexpr int kHTMin = 512, kHTMax = 4096;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -33,6 +35,7 @@ struct Plan {
   // assembly geometry
   int s1 = 0, s2 = 0, p2 = 1, nb = 0;  // bucket / sub-bucket shifts, sub-buckets per bucket, buckets
   int colbits = 1;                     // bits of a column index
+  int ht = 2048;                       // pass-3 hash slots
   int tile = 0;                        // elements (= threads) per pass-1 workgroup
   int64_t ntiles = 0, nsub = 0, nhist = 0, nseg_max = 0;
   size_t lds1 = 0, lds2 = 0;
@@ -74,7 +77,6 @@ int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p) {
     }
     if (tu->sub_bits < 0 || tu->sub_bits > 8 || tu->bucket_bits < 0 || tu->bucket_bits > 30) return KB_EINVAL;
     if (tu->bucket_bits && tu->sub_bits && tu->sub_bits > tu->bucket_bits) return KB_EINVAL;
-    if (tu->bucket_bits && tu->bucket_bits - (tu->sub_bits ? tu->sub_bits : 0) > 12) return KB_EINVAL;
     bucket_bits = tu->bucket_bits;
     sub_bits = tu->sub_bits;
   }
@@ -91,9 +93,12 @@ int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p) {
     p->s2 = sub_bits;
   } else {
     int s2 = 0;
-    while (s2 < s2_max && ((double)(1 << (s2 + 1))) * u_row <= 0.35 * kHT3) ++s2;
+    while (s2 < s2_max && ((double)(1 << (s2 + 1))) * u_row <= kSubEntries) ++s2;
     p->s2 = s2;
   }
+  // hash slots: about four per expected distinct entry (short probe chains)
+  p->ht = kHTMin;
+  while (p->ht < kHTMax && p->ht < 4.0 * (double)(1 << p->s2) * u_row) p->ht *= 2;
   if (bucket_bits) {
     p->s1 = bucket_bits < p->s2 ? p->s2 : bucket_bits;
   } else {
@@ -106,11 +111,14 @@ int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p) {
   p->p2 = 1 << (p->s1 - p->s2);
   p->nb = (int)div_up(p->nn, (int64_t)1 << p->s1);
   p->nsub = (int64_t)p->nb * p->p2;
-  // pass-1 tiles: one element per lane, pairs staged in LDS as (8-byte key, value)
-  if (p->nen == 4)
-    p->tile = prec == KB_FP64 ? 768 : 1024;
-  else
-    p->tile = prec == KB_FP64 ? 192 : 256;
+  // pass-1 tiles: one element per lane, pairs staged in LDS as (8-byte key, value);
+  // `block` may pick the half-size tile (two workgroups per CU)
+  {
+    const int big = p->nen == 4 ? (prec == KB_FP64 ? 768 : 1024) : (prec == KB_FP64 ? 192 : 256);
+    const int small = big / 2 % 64 == 0 ? big / 2 : 64 * ((big / 2 + 63) / 64);
+    p->tile = big;
+    if (tu && (tu->block == big || tu->block == small)) p->tile = tu->block;
+  }
   p->ntiles = div_up(p->nel, p->tile);
   p->nhist = (int64_t)p->nb * p->ntiles;
   p->nseg_max = div_up(p->T, kSeg) + p->nb;
@@ -125,13 +133,14 @@ int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p) {
   };
   const size_t T = (size_t)p->T;
   const int64_t scan_n = std::max(std::max(p->nhist, p->nseg_max * p->p2), p->nsub + 1);
+  // scan outputs hold n + 1 words: the scan writes its total after the last entry
   p->o_hist = take(4 * (size_t)p->nhist);
-  p->o_histT = take(4 * (size_t)p->nhist);
+  p->o_histT = take(4 * ((size_t)p->nhist + 1));
   p->o_part = take(4 * (size_t)(div_up(scan_n, kScanChunk) + 1));
   p->o_total = take(8);
   p->o_bstart = take(4 * ((size_t)p->nb + 1));
   p->o_segbase = take(4 * ((size_t)p->nb + 1));
-  p->o_hist2 = take(4 * (size_t)(p->nseg_max * p->p2));
+  p->o_hist2 = take(4 * ((size_t)(p->nseg_max * p->p2) + 1));
   p->o_emax = take(4);
   p->o_row1 = take(4 * T);
   p->o_col1 = take(4 * T);
@@ -167,7 +176,8 @@ struct Events {
 
 unsigned grid_for(int64_t n, int block) { return (unsigned)div_up(n, block); }
 
-// exclusive scan in[0..n) -> out[0..n], total64 optional (in-place allowed)
+// exclusive scan in[0..n) -> out[0..n] (out holds n + 1 words), total64 optional
+// (in-place allowed)
 int scan(const int32_t* in, int64_t n, int32_t* part, int32_t* out, int64_t* total64, hipStream_t s) {
   if (n == 0) {
     k_scan_empty<<<1, 1, 0, s>>>(out, total64);
@@ -198,12 +208,10 @@ bool set_lds(K kernel, size_t bytes) {
          hipSuccess;
 }
 
-template <int NEN, Prec P, bool FROM_VALUES>
-int launch_pass1(const Plan& p, const kb_mesh* m, const void* klow, unsigned char* ws, uint32_t* status,
-                 hipStream_t s) {
+template <int NEN, Prec P, bool FROM_VALUES, int BLOCK>
+int launch_pass1_block(const Plan& p, const kb_mesh* m, const void* klow, unsigned char* ws, uint32_t* status,
+                       hipStream_t s) {
   using V = typename PrecTraits<P>::V;
-  constexpr int BLOCK = NEN == 4 ? (P == Prec::F64 ? 768 : 1024) : (P == Prec::F64 ? 192 : 256);
-  if (p.tile != BLOCK) return KB_EINVAL;
   auto kern = k_pass1<NEN, P, FROM_VALUES, BLOCK>;
   if (!set_lds(kern, p.lds1)) return KB_EHIP;
   kern<<<(unsigned)p.ntiles, BLOCK, p.lds1, s>>>(m->conn, m->coords, m->coef, (const V*)klow, p.nel, p.nn, p.tau,
@@ -212,6 +220,24 @@ int launch_pass1(const Plan& p, const kb_mesh* m, const void* klow, unsigned cha
                                                 (V*)(ws + p.o_val1), (uint32_t*)(ws + p.o_emax), status);
   KB_LAUNCH_CHECK();
   return KB_OK;
+}
+
+// pass-1 tile sizes (elements = lanes per workgroup): {small, default} per element and
+// value size; the staging LDS is tile * pairs * (8 + value bytes)
+template <int NEN, Prec P>
+struct TileSizes {
+  static constexpr int big = NEN == 4 ? (P == Prec::F64 ? 768 : 1024) : (P == Prec::F64 ? 192 : 256);
+  static constexpr int small = big / 2 >= 64 && (big / 2) % 64 == 0 ? big / 2 : 64 * ((big / 2 + 63) / 64);
+};
+
+template <int NEN, Prec P, bool FROM_VALUES>
+int launch_pass1(const Plan& p, const kb_mesh* m, const void* klow, unsigned char* ws, uint32_t* status,
+                 hipStream_t s) {
+  if (p.tile == TileSizes<NEN, P>::big)
+    return launch_pass1_block<NEN, P, FROM_VALUES, TileSizes<NEN, P>::big>(p, m, klow, ws, status, s);
+  if (p.tile == TileSizes<NEN, P>::small)
+    return launch_pass1_block<NEN, P, FROM_VALUES, TileSizes<NEN, P>::small>(p, m, klow, ws, status, s);
+  return KB_EINVAL;
 }
 
 template <typename V>
@@ -249,7 +275,21 @@ int assemble_tail(const Plan& p, unsigned char* ws, int32_t* row_ptr, int32_t* c
   }
   KB_TRY(ev.rec(KB_STAGE_REDUCE));
   if (p.nsub > 0) {
-    k_pass3<V><<<(unsigned)p.nsub, 256, 0, s>>>(key2, val2, sbb, p.s2, p.colbits, p.nn, emax, tcol, tval, ucnt, usub);
+    const unsigned g3 = (unsigned)p.nsub;
+    switch (p.ht) {
+      case 512:
+        k_pass3<V, 512><<<g3, 256, 0, s>>>(key2, val2, sbb, p.s2, p.colbits, p.nn, emax, tcol, tval, ucnt, usub);
+        break;
+      case 1024:
+        k_pass3<V, 1024><<<g3, 256, 0, s>>>(key2, val2, sbb, p.s2, p.colbits, p.nn, emax, tcol, tval, ucnt, usub);
+        break;
+      case 2048:
+        k_pass3<V, 2048><<<g3, 256, 0, s>>>(key2, val2, sbb, p.s2, p.colbits, p.nn, emax, tcol, tval, ucnt, usub);
+        break;
+      default:
+        k_pass3<V, 4096><<<g3, 256, 0, s>>>(key2, val2, sbb, p.s2, p.colbits, p.nn, emax, tcol, tval, ucnt, usub);
+        break;
+    }
     KB_LAUNCH_CHECK();
   }
   KB_TRY(ev.rec(KB_STAGE_COMPRESS));

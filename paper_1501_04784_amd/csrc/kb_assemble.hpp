@@ -36,7 +36,6 @@
 namespace kb {
 
 constexpr uint32_t kEmptyKey = 0xFFFFFFFFu;  // packed keys never use bit 31
-constexpr int kHT3 = 2048;                   // pass-3 hash slots
 
 // ----------------------------------------------------------------- block helpers
 // exclusive scan of one uint32 per thread across the block; *total = block sum.
@@ -124,6 +123,22 @@ __device__ __forceinline__ void to_fixed(double v, int F, uint64_t& lo, uint64_t
     lo = ~lo + 1;
     hi = ~hi + (lo == 0 ? 1ull : 0ull);
   }
+}
+
+// q (two's complement 128-bit, |q| < 2^95) as c0 + c1 * 2^48 with c0 in [0, 2^48)
+// and c1 signed: sums of up to 2^16 such terms fit in one unsigned / signed 64-bit
+// word each, so they can be accumulated without carries (and in any order).
+__device__ __forceinline__ void split48(uint64_t lo, uint64_t hi, uint64_t& c0, int64_t& c1) {
+  c0 = lo & ((1ull << 48) - 1);
+  c1 = (int64_t)((lo >> 48) | (hi << 16));
+}
+
+// chunk sums back to the exact 128-bit value
+__device__ __forceinline__ void join48(uint64_t s0, int64_t s1, uint64_t& lo, uint64_t& hi) {
+  const uint64_t a_lo = (uint64_t)s1 << 48;
+  const uint64_t a_hi = (uint64_t)(s1 >> 16);  // arithmetic shift keeps the sign
+  lo = s0 + a_lo;
+  hi = a_hi + (lo < s0 ? 1ull : 0ull);
 }
 
 // exact 128-bit value -> double, correctly rounded; then scaled by 2^-F
@@ -404,14 +419,21 @@ __global__ __launch_bounds__(256) void k_scatter2(const uint32_t* __restrict__ i
   const uint32_t i0 = bs + s * SEG, i1 = (i0 + SEG < be) ? i0 + SEG : be;
   const uint32_t mask = (uint32_t)p2 - 1, rmask = (1u << s2) - 1;
   constexpr int PER = SEG / 256;
-  uint32_t rr[PER];
+  uint32_t rr[PER], cc[PER];
+  V vv[PER];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const uint32_t i = i0 + q * 256 + threadIdx.x;
     if (i < i1) {
       rr[q] = irow[i];
-      atomicAdd(&s_cnt[(rr[q] >> s2) & mask], 1u);
+      cc[q] = icol[i];
+      vv[q] = ival[i];
     }
+  }
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const uint32_t i = i0 + q * 256 + threadIdx.x;
+    if (i < i1) atomicAdd(&s_cnt[(rr[q] >> s2) & mask], 1u);
   }
   __syncthreads();
   for (int j = threadIdx.x; j < p2; j += blockDim.x) s_cur[j] = s_cnt[j];
@@ -425,8 +447,8 @@ __global__ __launch_bounds__(256) void k_scatter2(const uint32_t* __restrict__ i
     if (i < i1) {
       const uint32_t j = (rr[q] >> s2) & mask;
       const uint32_t pos = atomicAdd(&s_cur[j], 1u);
-      s_key[pos] = ((rr[q] & rmask) << colbits) | icol[i];
-      s_val[pos] = ival[i];
+      s_key[pos] = ((rr[q] & rmask) << colbits) | cc[q];
+      s_val[pos] = vv[q];
       s_sb[pos] = (uint16_t)j;
     }
   }
@@ -505,16 +527,15 @@ __device__ void pass3_global(uint32_t* key, V* val, int64_t n, int64_t r0, int R
 
 // One workgroup per sub-bucket g (rows [g << s2, ...)).  Writes its unique entries in
 // CSR order to tcol/tval[sbb[g] + f], per-row unique counts to ucnt, total to usub[g].
-template <typename V>
+template <typename V, int HT>
 __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* __restrict__ ival,
                                                const uint32_t* __restrict__ sbb, int s2, int colbits, int64_t n_node,
                                                const uint32_t* __restrict__ emax, int32_t* __restrict__ tcol,
                                                V* __restrict__ tval, int32_t* __restrict__ ucnt,
                                                uint32_t* __restrict__ usub) {
-  constexpr int HT = kHT3;
   __shared__ uint32_t s_key[HT];
-  __shared__ unsigned long long s_lo[HT];
-  __shared__ unsigned long long s_hi[HT];
+  __shared__ unsigned long long s_lo[HT];  // sum of low 48-bit chunks
+  __shared__ unsigned long long s_hi[HT];  // sum of signed high chunks
   __shared__ uint16_t s_w[HT];     // index of the slot within its row
   __shared__ uint16_t s_list[HT];  // slots grouped by row
   __shared__ uint32_t s_rc[256];   // entries per row
@@ -536,34 +557,50 @@ __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* _
     s_hi[h] = 0ull;
   }
   for (int r = threadIdx.x; r < 256; r += blockDim.x) s_rc[r] = 0;
-  if (threadIdx.x == 0) s_over = 0;
+  // more than 2^16 pairs could overflow the chunk sums: take the global path
+  if (threadIdx.x == 0) s_over = (end - beg > (1u << 16)) ? 1u : 0u;
   __syncthreads();
-  // stream the pairs into the table
-  for (uint32_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
-    const uint32_t key = ikey[i];
-    uint64_t qlo, qhi;
-    to_fixed((double)ival[i], F, qlo, qhi);
-    uint32_t h = key_hash(key) & (HT - 1);
-    int probes = 0;
-    bool found = false;
-    while (probes < HT) {
-      uint32_t k = s_key[h];
-      if (k == kEmptyKey) k = atomicCAS(&s_key[h], kEmptyKey, key);
-      if (k == kEmptyKey || k == key) {
-        found = true;
-        break;
+  // stream the pairs into the table, eight per lane in flight
+  if (!s_over) {
+    for (uint32_t i0 = beg + threadIdx.x; i0 < end; i0 += 8 * 256) {
+      uint32_t kk[8];
+      double vv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const uint32_t i = i0 + u * 256;
+        kk[u] = i < end ? ikey[i] : kEmptyKey;
+        vv[u] = i < end ? (double)ival[i] : 0.0;
       }
-      h = (h + 1) & (HT - 1);
-      ++probes;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const uint32_t key = kk[u];
+        if (key == kEmptyKey) continue;
+        uint64_t qlo, qhi;
+        to_fixed(vv[u], F, qlo, qhi);
+        uint32_t h = key_hash(key) & (HT - 1);
+        int probes = 0;
+        bool found = false;
+        while (probes < HT) {
+          uint32_t k = s_key[h];
+          if (k == kEmptyKey) k = atomicCAS(&s_key[h], kEmptyKey, key);
+          if (k == kEmptyKey || k == key) {
+            found = true;
+            break;
+          }
+          h = (h + 1) & (HT - 1);
+          ++probes;
+        }
+        if (!found) {
+          s_over = 1;
+          continue;
+        }
+        uint64_t c0;
+        int64_t c1;
+        split48(qlo, qhi, c0, c1);
+        if (c0) atomicAdd(&s_lo[h], (unsigned long long)c0);
+        if (c1) atomicAdd(&s_hi[h], (unsigned long long)c1);
+      }
     }
-    if (!found) {
-      s_over = 1;
-      break;
-    }
-    const unsigned long long old = atomicAdd(&s_lo[h], (unsigned long long)qlo);
-    const uint64_t carry = (old + qlo < old) ? 1ull : 0ull;
-    const uint64_t add_hi = qhi + carry;
-    if (add_hi) atomicAdd(&s_hi[h], (unsigned long long)add_hi);
   }
   __syncthreads();
   if (s_over) {
@@ -594,7 +631,9 @@ __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* _
     for (uint32_t q = 0; q < nr; ++q) rank += ((s_key[s_list[ro + q]] & cmask) < col) ? 1u : 0u;
     const uint32_t f = ro + rank;
     tcol[beg + f] = (int32_t)col;
-    tval[beg + f] = (V)from_fixed(s_lo[h], s_hi[h], F);
+    uint64_t lo, hi;
+    join48(s_lo[h], (int64_t)s_hi[h], lo, hi);
+    tval[beg + f] = (V)from_fixed(lo, hi, F);
   }
   for (int r = threadIdx.x; r < R; r += blockDim.x) ucnt[r0 + r] = (int32_t)s_rc[r];
   if (threadIdx.x == 0) usub[g] = U;

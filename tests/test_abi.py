@@ -92,7 +92,7 @@ def test_plan_errors():
     assert _plan(8, 10, 10, tuning=KbTuning(0, 0, 0.5, 0, None))[0] == _lib.KB_EINVAL  # tau <= 1
     assert _plan(8, 10, 10, tuning=KbTuning(0, 0, 0.0, 9, None))[0] == _lib.KB_EINVAL  # sub-bucket bits > 8
     assert _plan(8, 10, 10, tuning=KbTuning(0, 3, 0.0, 5, None))[0] == _lib.KB_EINVAL  # sub > bucket
-    assert _plan(8, 10, 10, tuning=KbTuning(0, 20, 0.0, 2, None))[0] == _lib.KB_EINVAL  # > 4096 sub-buckets
+    assert _plan(8, 10, 10, tuning=KbTuning(0, 20, 0.0, 2, None))[0] == _lib.KB_EINVAL  # > 1024 sub-buckets
     assert _plan(8, 10, 10, tuning=KbTuning(512, 10, 8.0, 4, None))[0] == 0
 
 

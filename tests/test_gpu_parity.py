@@ -89,6 +89,20 @@ def test_build_parity_medium(elem, n, prec):
     assert err <= TOL[prec]
 
 
+@pytest.mark.parametrize("elem", [8, 4])
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6, 7, 8, 11, 13, 16, 21])
+def test_build_parity_size_sweep(elem, n):
+    """Many mesh sizes: workspace regions, tiles and buckets take many shapes."""
+    m = meshgen.box_mesh(elem, n, n + 1, max(1, n - 1), jitter=0.2, coef=(0.1, 10), permute_nodes=True,
+                         permute_elems=True, seed=100 + n)
+    r = gpu_build(m, "fp64")
+    rp, col, val = np_csr(r)
+    orp, ocol, oval, _ = oracle.build_mesh(m)
+    np.testing.assert_array_equal(rp, orp)
+    np.testing.assert_array_equal(col, ocol)
+    assert scaled_error(orp, ocol, val, oval) <= TOL["fp64"]
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("name", ["c2_hex13", "c3_tet9"])
 def test_assemble_parity(name, prec):
@@ -158,11 +172,13 @@ def _fan(n_tets, center_last, seed=0):
     return meshgen.Mesh(4, conn, X, np.exp(rng.uniform(-2, 2, n_tets)))
 
 
-@pytest.mark.parametrize("center_last", [False, True])
+@pytest.mark.parametrize("n_tets,center_last", [(5000, False), (5000, True), (20000, True)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32fb64"])
-def test_heavy_row(center_last, prec):
-    """A node shared by 5000 elements: its row exceeds one row block's LDS capacity."""
-    m = _fan(5000, center_last)
+def test_heavy_row(n_tets, center_last, prec):
+    """A node shared by thousands of elements.  With the centre last, its row holds
+    3 n + 1 distinct entries (more than any LDS hash table: global path); with 20000 tets
+    its sub-bucket also exceeds 2^16 pairs (the chunk-sum bound: global path)."""
+    m = _fan(n_tets, center_last)
     r = gpu_build(m, prec)
     rp, col, val = np_csr(r)
     orp, ocol, oval, _ = oracle.build_mesh(m)
