@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sample", type=int, default=10_000_000, help="elements in the oracle's timed sample")
     ap.add_argument("--profile-steps", action="store_true", help="no stage events (for profiler runs)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (counter calibration)")
     ap.add_argument("--block", type=int, default=0, help="tuning: element tile / block size")
     ap.add_argument("--bucket-bits", type=int, default=0, help="tuning: log2 rows per first-level bucket")
     ap.add_argument("--sub-bits", type=int, default=0, help="tuning: log2 rows per sub-bucket")
@@ -137,6 +139,13 @@ def main():
     import meshgen
     import paper_1501_04784_amd as kb
 
+    if args.calib_copy_mib:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE calibrate the counters
+        src = torch.ones(args.calib_copy_mib << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     cid, desc, default_prec = WORKLOADS[args.workload]
     prec = args.prec or default_prec
     print(f"[bench] generating workload {args.workload}: {desc}", file=sys.stderr, flush=True)

@@ -20,6 +20,7 @@ constexpr size_t kAlign = 256;
 constexpr float kDefaultTau = 16.0f;
 constexpr int kDefaultBlock = 256;
 constexpr int kSeg = 4096;         // pairs per pass-2 segment
+constexpr int kSegThreads = 512;   // threads per pass-2 scatter workgroup
 constexpr int kTargetBuckets = 512;  // first-level buckets (pass-1 run length)
 constexpr double kSubEntries = 300;   // target distinct entries per sub-bucket
 constexpr int kHTMin = 512, kHTMax = 4096;
@@ -40,7 +41,7 @@ struct Plan {
   int64_t ntiles = 0, nsub = 0, nhist = 0, nseg_max = 0;
   size_t lds1 = 0, lds2 = 0;
   // workspace offsets
-  size_t o_hist = 0, o_histT = 0, o_part = 0, o_total = 0, o_bstart = 0, o_segbase = 0, o_hist2 = 0, o_emax = 0,
+  size_t o_coords4 = 0, o_hist = 0, o_histT = 0, o_part = 0, o_total = 0, o_bstart = 0, o_segbase = 0, o_hist2 = 0, o_emax = 0,
          o_row1 = 0, o_col1 = 0, o_val1 = 0, o_key2 = 0, o_val2 = 0, o_sbb = 0, o_ucnt = 0, o_usub = 0, o_ubase = 0,
          total = 0;
 };
@@ -123,7 +124,7 @@ int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p) {
   p->nhist = (int64_t)p->nb * p->ntiles;
   p->nseg_max = div_up(p->T, kSeg) + p->nb;
   p->lds1 = (size_t)p->tile * p->te * (8 + p->vbytes) + 3 * 4 * (size_t)p->nb + 4 * (p->tile / 64 + 2);
-  p->lds2 = (size_t)kSeg * (p->vbytes + 4 + 2) + 3 * 4 * (size_t)p->p2 + 4 * 5;
+  p->lds2 = (size_t)kSeg * (p->vbytes + 4 + 2) + 3 * 4 * (size_t)p->p2 + 4 * (kSegThreads / 64 + 1);
   if (p->lds1 > 163840 || p->lds2 > 163840) return KB_EINVAL;
   size_t off = 0;
   auto take = [&](size_t bytes) {  // every region at least one aligned block
@@ -133,6 +134,7 @@ int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p) {
   };
   const size_t T = (size_t)p->T;
   const int64_t scan_n = std::max(std::max(p->nhist, p->nseg_max * p->p2), p->nsub + 1);
+  p->o_coords4 = take(32 * (size_t)p->nn);
   // scan outputs hold n + 1 words: the scan writes its total after the last entry
   p->o_hist = take(4 * (size_t)p->nhist);
   p->o_histT = take(4 * ((size_t)p->nhist + 1));
@@ -214,7 +216,8 @@ int launch_pass1_block(const Plan& p, const kb_mesh* m, const void* klow, unsign
   using V = typename PrecTraits<P>::V;
   auto kern = k_pass1<NEN, P, FROM_VALUES, BLOCK>;
   if (!set_lds(kern, p.lds1)) return KB_EHIP;
-  kern<<<(unsigned)p.ntiles, BLOCK, p.lds1, s>>>(m->conn, m->coords, m->coef, (const V*)klow, p.nel, p.nn, p.tau,
+  kern<<<(unsigned)p.ntiles, BLOCK, p.lds1, s>>>(m->conn, (const double4*)(ws + p.o_coords4), m->coef, (const V*)klow,
+                                                p.nel, p.nn, p.tau,
                                                 p.s1, p.nb, (const uint32_t*)(ws + p.o_hist),
                                                 (uint32_t*)(ws + p.o_row1), (uint32_t*)(ws + p.o_col1),
                                                 (V*)(ws + p.o_val1), (uint32_t*)(ws + p.o_emax), status);
@@ -268,9 +271,10 @@ int assemble_tail(const Plan& p, unsigned char* ws, int32_t* row_ptr, int32_t* c
     KB_TRY(scan((const int32_t*)hist2, p.nseg_max * p.p2, part, (int32_t*)hist2, nullptr, s));
     k_subbucket_starts<<<grid_for(p.nsub + 1, 256), 256, 0, s>>>(hist2, bstart, segbase, p.nb, p.p2, sbb);
     KB_LAUNCH_CHECK();
-    auto k2 = k_scatter2<V, kSeg>;
+    auto k2 = k_scatter2<V, kSeg, kSegThreads>;
     if (!set_lds(k2, p.lds2)) return KB_EHIP;
-    k2<<<gs, 256, p.lds2, s>>>(row1, col1, val1, bstart, segbase, hist2, p.nb, p.s2, p.p2, p.colbits, key2, val2);
+    k2<<<gs, kSegThreads, p.lds2, s>>>(row1, col1, val1, bstart, segbase, hist2, p.nb, p.s2, p.p2, p.colbits, key2,
+                                      val2);
     KB_LAUNCH_CHECK();
   }
   KB_TRY(ev.rec(KB_STAGE_REDUCE));
@@ -344,6 +348,11 @@ int build_impl(const Plan& p, const kb_mesh* m, const void* klow, unsigned char*
   }
   KB_TRY(ev.rec(KB_STAGE_INTEGRATE));
   if (p.ntiles > 0 && p.nb > 0) {
+    if (!klow && p.nn > 0) {
+      k_pad_coords<<<(unsigned)std::min<int64_t>(div_up(p.nn, 256), 8192), 256, 0, s>>>(
+          m->coords, p.nn, (double4*)(ws + p.o_coords4));
+      KB_LAUNCH_CHECK();
+    }
     if (klow) {
       KB_TRY((launch_pass1<NEN, P, true>(p, m, klow, ws, status, s)));
     } else {

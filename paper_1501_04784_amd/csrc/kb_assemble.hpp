@@ -9,7 +9,8 @@
 //   offsets  transpose + exclusive scan + transpose back: each tile's write offset in
 //            each bucket; bucket boundaries.
 //   pass 1   per tile (one element per lane): integrate the element (or read given
-//            values), stage its pairs in LDS grouped by bucket, write each bucket's run
+//            values; coordinates come from a padded 32-byte-per-node copy made by
+//            k_pad_coords), stage its pairs in LDS grouped by bucket, write each bucket's run
 //            at the tile's offset as (row, col, value) arrays.  Also the largest value
 //            exponent, which fixes the exact-sum scale below.
 //   pass 2   per fixed-size segment of a bucket: histogram of sub-buckets
@@ -239,7 +240,7 @@ __global__ __launch_bounds__(256) void k_segments(const uint32_t* __restrict__ b
 // Per tile of BLOCK elements (one per lane): produce the element's lower pairs, group
 // them by bucket in LDS, write runs to (orow, ocol, oval).
 template <int NEN, Prec P, bool FROM_VALUES, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_pass1(const int32_t* __restrict__ conn, const double* __restrict__ coords,
+__global__ __launch_bounds__(BLOCK) void k_pass1(const int32_t* __restrict__ conn, const double4* __restrict__ coords4,
                                                const double* __restrict__ coef,
                                                const typename PrecTraits<P>::V* __restrict__ klow, int64_t n_elem,
                                                int64_t n_node, float tau, int s1, int nb,
@@ -296,7 +297,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass1(const int32_t* __restrict__ con
       }
       if (!finite) flags |= KB_F_NONFINITE;
     } else {
-      element_values<NEN, P>(coords, coef, e, E, tau, k, &flags, &fb);
+      element_values<NEN, P>(NodesPadded{coords4}, coef, e, E, tau, k, &flags, &fb);
     }
     int em = 0;
 #pragma unroll
@@ -391,8 +392,8 @@ __global__ void k_subbucket_starts(const uint32_t* __restrict__ off2, const uint
 }
 
 // scatter a segment into its sub-buckets; output key = row_local << colbits | col
-template <typename V, int SEG>
-__global__ __launch_bounds__(256) void k_scatter2(const uint32_t* __restrict__ irow, const uint32_t* __restrict__ icol,
+template <typename V, int SEG, int NT>
+__global__ __launch_bounds__(NT) void k_scatter2(const uint32_t* __restrict__ irow, const uint32_t* __restrict__ icol,
                                                   const V* __restrict__ ival, const uint32_t* __restrict__ bstart,
                                                   const uint32_t* __restrict__ segbase,
                                                   const uint32_t* __restrict__ off2, int nb, int s2, int p2,
@@ -404,7 +405,7 @@ __global__ __launch_bounds__(256) void k_scatter2(const uint32_t* __restrict__ i
   uint32_t* s_cnt = (uint32_t*)(s_sb + SEG);    // [p2] local starts
   uint32_t* s_cur = s_cnt + p2;                 // [p2]
   uint32_t* s_off = s_cur + p2;                 // [p2] global offsets
-  uint32_t* s_scan = s_off + p2;                // [5]
+  uint32_t* s_scan = s_off + p2;                // [NT/64 + 1]
   int b;
   uint32_t s;
   if (!find_segment(blockIdx.x, segbase, nb, b, s)) return;
@@ -418,12 +419,12 @@ __global__ __launch_bounds__(256) void k_scatter2(const uint32_t* __restrict__ i
   const uint32_t bs = bstart[b], be = bstart[b + 1];
   const uint32_t i0 = bs + s * SEG, i1 = (i0 + SEG < be) ? i0 + SEG : be;
   const uint32_t mask = (uint32_t)p2 - 1, rmask = (1u << s2) - 1;
-  constexpr int PER = SEG / 256;
+  constexpr int PER = SEG / NT;
   uint32_t rr[PER], cc[PER];
   V vv[PER];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
-    const uint32_t i = i0 + q * 256 + threadIdx.x;
+    const uint32_t i = i0 + q * NT + threadIdx.x;
     if (i < i1) {
       rr[q] = irow[i];
       cc[q] = icol[i];
@@ -432,7 +433,7 @@ __global__ __launch_bounds__(256) void k_scatter2(const uint32_t* __restrict__ i
   }
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
-    const uint32_t i = i0 + q * 256 + threadIdx.x;
+    const uint32_t i = i0 + q * NT + threadIdx.x;
     if (i < i1) atomicAdd(&s_cnt[(rr[q] >> s2) & mask], 1u);
   }
   __syncthreads();
@@ -443,7 +444,7 @@ __global__ __launch_bounds__(256) void k_scatter2(const uint32_t* __restrict__ i
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
-    const uint32_t i = i0 + q * 256 + threadIdx.x;
+    const uint32_t i = i0 + q * NT + threadIdx.x;
     if (i < i1) {
       const uint32_t j = (rr[q] >> s2) & mask;
       const uint32_t pos = atomicAdd(&s_cur[j], 1u);
@@ -556,7 +557,7 @@ __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* _
     s_lo[h] = 0ull;
     s_hi[h] = 0ull;
   }
-  for (int r = threadIdx.x; r < 256; r += blockDim.x) s_rc[r] = 0;
+  for (int r = threadIdx.x; r < (1 << s2); r += blockDim.x) s_rc[r] = 0;
   // more than 2^16 pairs could overflow the chunk sums: take the global path
   if (threadIdx.x == 0) s_over = (end - beg > (1u << 16)) ? 1u : 0u;
   __syncthreads();
@@ -614,9 +615,10 @@ __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* _
     if (k != kEmptyKey) s_w[h] = (uint16_t)atomicAdd(&s_rc[k >> colbits], 1u);
   }
   __syncthreads();
-  for (int r = threadIdx.x; r < 256; r += blockDim.x) s_ro[r] = s_rc[r];
+  const int RB = 1 << s2;  // rows of a full sub-bucket (<= 256)
+  for (int r = threadIdx.x; r < RB; r += blockDim.x) s_ro[r] = s_rc[r];
   __syncthreads();
-  const uint32_t U = block_scan_array(s_ro, 256, s_scan);
+  const uint32_t U = block_scan_array(s_ro, RB, s_scan);
   for (int h = threadIdx.x; h < HT; h += blockDim.x) {
     const uint32_t k = s_key[h];
     if (k != kEmptyKey) s_list[s_ro[k >> colbits] + s_w[h]] = (uint16_t)h;

@@ -178,36 +178,66 @@ struct PrecTraits<Prec::F32FB> {
   using V = float;
 };
 
+// Node coordinate sources: [n][3] as given, or padded [n][4] (one aligned 32-byte
+// record per node, so each random gather touches a single cache line).
+struct NodesXYZ {
+  const double* __restrict__ p;
+  __device__ __forceinline__ void get(int32_t n, double (&x)[3]) const {
+    const double* q = p + (int64_t)n * 3;
+    x[0] = q[0];
+    x[1] = q[1];
+    x[2] = q[2];
+  }
+};
+struct NodesPadded {
+  const double4* __restrict__ p;
+  __device__ __forceinline__ void get(int32_t n, double (&x)[3]) const {
+    const double4 v = p[n];
+    x[0] = v.x;
+    x[1] = v.y;
+    x[2] = v.z;
+  }
+};
+
+__global__ void k_pad_coords(const double* __restrict__ c, int64_t n, double4* __restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = make_double4(c[3 * i], c[3 * i + 1], c[3 * i + 2], 0.0);
+}
+
 // Integrate element e into k (value type V, c applied).  Adds flag bits to *f and
 // counts a fallback in *fb.  E must be valid.
-template <int NEN, Prec P>
-__device__ __forceinline__ void element_values(const double* __restrict__ coords, const double* __restrict__ coef,
-                                               int64_t e, const int32_t (&E)[NEN], float tau,
+template <int NEN, Prec P, typename NODES>
+__device__ __forceinline__ void element_values(const NODES& nodes, const double* __restrict__ coef, int64_t e,
+                                               const int32_t (&E)[NEN], float tau,
                                                typename PrecTraits<P>::V (&k)[ElemTraits<NEN>::T], uint32_t* f,
                                                uint32_t* fb) {
   constexpr int T = ElemTraits<NEN>::T;
   using V = typename PrecTraits<P>::V;
   double X0[3];
-  X0[0] = coords[(int64_t)E[0] * 3 + 0];
-  X0[1] = coords[(int64_t)E[0] * 3 + 1];
-  X0[2] = coords[(int64_t)E[0] * 3 + 2];
+  nodes.get(E[0], X0);
   const double c = coef[e];
   bool ok;
   if constexpr (P == Prec::F64) {
     double X[NEN][3];
     X[0][0] = X[0][1] = X[0][2] = 0.0;
 #pragma unroll
-    for (int a = 1; a < NEN; ++a)
+    for (int a = 1; a < NEN; ++a) {
+      double xa[3];
+      nodes.get(E[a], xa);
 #pragma unroll
-      for (int j = 0; j < 3; ++j) X[a][j] = coords[(int64_t)E[a] * 3 + j] - X0[j];
+      for (int j = 0; j < 3; ++j) X[a][j] = xa[j] - X0[j];
+    }
     ok = integrate<NEN, double, double, false>(X, k, 0.0, nullptr);
   } else {
     float X[NEN][3];
     X[0][0] = X[0][1] = X[0][2] = 0.f;
 #pragma unroll
-    for (int a = 1; a < NEN; ++a)
+    for (int a = 1; a < NEN; ++a) {
+      double xa[3];
+      nodes.get(E[a], xa);
 #pragma unroll
-      for (int j = 0; j < 3; ++j) X[a][j] = (float)(coords[(int64_t)E[a] * 3 + j] - X0[j]);
+      for (int j = 0; j < 3; ++j) X[a][j] = (float)(xa[j] - X0[j]);
+    }
     bool need_fb = false;
     ok = integrate<NEN, float, float, P == Prec::F32FB>(X, k, tau, &need_fb);
     if constexpr (P == Prec::F32FB) {
@@ -216,9 +246,12 @@ __device__ __forceinline__ void element_values(const double* __restrict__ coords
         double Xd[NEN][3];
         Xd[0][0] = Xd[0][1] = Xd[0][2] = 0.0;
 #pragma unroll
-        for (int a = 1; a < NEN; ++a)
+        for (int a = 1; a < NEN; ++a) {
+          double xa[3];
+          nodes.get(E[a], xa);
 #pragma unroll
-          for (int j = 0; j < 3; ++j) Xd[a][j] = coords[(int64_t)E[a] * 3 + j] - X0[j];
+          for (int j = 0; j < 3; ++j) Xd[a][j] = xa[j] - X0[j];
+        }
         ok = integrate<NEN, double, float, false>(Xd, k, 0.0, nullptr);
         *fb += 1;
       }
@@ -254,7 +287,7 @@ __global__ __launch_bounds__(256) void k_integrate_store(const int32_t* __restri
 #pragma unroll
     for (int p = 0; p < T; ++p) k[p] = V(0);
   } else {
-    element_values<NEN, P>(coords, coef, e, E, tau, k, &f, &fb);
+    element_values<NEN, P>(NodesXYZ{coords}, coef, e, E, tau, k, &f, &fb);
   }
 #pragma unroll
   for (int p = 0; p < T; ++p) out[e * T + p] = k[p];
