@@ -134,6 +134,39 @@ __device__ __forceinline__ void split48(uint64_t lo, uint64_t hi, uint64_t& c0, 
   c1 = (int64_t)((lo >> 48) | (hi << 16));
 }
 
+// The two chunks of split48 computed directly from |q| = m * 2^sh (m < 2^53) and the
+// sign, without forming the 128-bit integer: c0 = q mod 2^48, c1 = floor(q / 2^48).
+// Same truncation toward zero as to_fixed; no branches.
+__device__ __forceinline__ void chunks_from_mag(uint64_t m, int sh, bool neg, uint64_t& c0, int64_t& c1) {
+  constexpr uint64_t M48 = (1ull << 48) - 1;
+  const uint64_t mag = sh >= 0 ? (sh < 64 ? m << sh : 0ull) : (-sh < 64 ? m >> -sh : 0ull);
+  const uint64_t lo = mag & M48;  // low 48 bits of the (truncated) magnitude
+  const int hs = 48 - sh;         // m >> hs is the magnitude above bit 48
+  const uint64_t hi = hs <= 0 ? m << -hs : (hs < 64 ? m >> hs : 0ull);
+  const uint64_t borrow = lo ? 1ull : 0ull;
+  c0 = neg ? ((1ull << 48) - lo) & M48 : lo;
+  c1 = neg ? -(int64_t)(hi + borrow) : (int64_t)hi;
+}
+
+// split48 chunks of trunc(v * 2^F) for a double or float value (non-finite: zero)
+__device__ __forceinline__ void to_chunks(double v, int F, uint64_t& c0, int64_t& c1) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const int E = (int)((b >> 52) & 0x7FF);
+  uint64_t m = b & ((1ull << 52) - 1);
+  m |= (E != 0) ? (1ull << 52) : 0ull;
+  m = (E == 0x7FF) ? 0ull : m;
+  chunks_from_mag(m, (E != 0 ? E : 1) - 1075 + F, (b >> 63) != 0, c0, c1);
+}
+__device__ __forceinline__ void to_chunks(float v, int F, uint64_t& c0, int64_t& c1) {
+  const uint32_t b = __float_as_uint(v);
+  const int E = (int)((b >> 23) & 0xFF);
+  uint32_t m = b & 0x7FFFFFu;
+  m |= (E != 0) ? 0x800000u : 0u;
+  m = (E == 0xFF) ? 0u : m;
+  // a float is m * 2^(E-150), the same value as its exact double
+  chunks_from_mag((uint64_t)m, (E != 0 ? E : 1) - 150 + F, (b >> 31) != 0, c0, c1);
+}
+
 // chunk sums back to the exact 128-bit value
 __device__ __forceinline__ void join48(uint64_t s0, int64_t s1, uint64_t& lo, uint64_t& hi) {
   const uint64_t a_lo = (uint64_t)s1 << 48;
@@ -259,13 +292,12 @@ __global__ __launch_bounds__(BLOCK) void k_pass1(const int32_t* __restrict__ con
   uint32_t* s_scan = s_cur + nb;                 // [BLOCK/64 + 1]
   uint32_t* s_emax = s_scan + (BLOCK / 64 + 1);  // [1]
 
-  const int64_t t = blockIdx.x;
+  const int64_t t = xcd_item(blockIdx.x, gridDim.x);
   for (int b = threadIdx.x; b < nb; b += BLOCK) {
     s_cnt[b] = 0;
     s_base[b] = off1[t * nb + b];
   }
   if (threadIdx.x == 0) *s_emax = 0;
-  __syncthreads();
   const int64_t e = t * BLOCK + threadIdx.x;
   int32_t E[NEN];
   bool valid = false;
@@ -273,6 +305,19 @@ __global__ __launch_bounds__(BLOCK) void k_pass1(const int32_t* __restrict__ con
     load_conn<NEN>(conn, e, E);
     valid = check_conn<NEN>(E, n_node) == 0;
   }
+  // tetrahedra: issue the coordinate gathers now, so that their latency hides behind
+  // the counting and scan below (bricks keep their larger node set out of the
+  // registers until it is needed)
+  constexpr bool kEarly = NEN == 4 && !FROM_VALUES;
+  double Xn[kEarly ? NEN : 1][3];
+  double c_e = 0.0;
+  if constexpr (kEarly) {
+    if (valid) {
+      gather_nodes<NEN>(NodesPadded{coords4}, E, Xn);
+      c_e = coef[e];
+    }
+  }
+  __syncthreads();
   int r[NEN];
   if (valid) {
     node_ranks<NEN>(E, r);
@@ -296,6 +341,8 @@ __global__ __launch_bounds__(BLOCK) void k_pass1(const int32_t* __restrict__ con
         finite = finite && isfinite((double)k[p]);
       }
       if (!finite) flags |= KB_F_NONFINITE;
+    } else if constexpr (kEarly) {
+      element_values_at<NEN, P>(Xn, c_e, tau, k, &flags, &fb);
     } else {
       element_values<NEN, P>(NodesPadded{coords4}, coef, e, E, tau, k, &flags, &fb);
     }
@@ -408,7 +455,7 @@ __global__ __launch_bounds__(NT) void k_scatter2(const uint32_t* __restrict__ ir
   uint32_t* s_scan = s_off + p2;                // [NT/64 + 1]
   int b;
   uint32_t s;
-  if (!find_segment(blockIdx.x, segbase, nb, b, s)) return;
+  if (!find_segment(xcd_item(blockIdx.x, gridDim.x), segbase, nb, b, s)) return;
   const uint32_t nseg = segbase[b + 1] - segbase[b];
   const int64_t hbase = (int64_t)segbase[b] * p2 + s;
   for (int j = threadIdx.x; j < p2; j += blockDim.x) {
@@ -528,21 +575,25 @@ __device__ void pass3_global(uint32_t* key, V* val, int64_t n, int64_t r0, int R
 
 // One workgroup per sub-bucket g (rows [g << s2, ...)).  Writes its unique entries in
 // CSR order to tcol/tval[sbb[g] + f], per-row unique counts to ucnt, total to usub[g].
+// Sub-buckets run in their natural order: under a random numbering the lower-triangle
+// pairs of a row grow with its id, so an even interleave keeps the XCDs balanced.
 template <typename V, int HT>
 __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* __restrict__ ival,
                                                const uint32_t* __restrict__ sbb, int s2, int colbits, int64_t n_node,
                                                const uint32_t* __restrict__ emax, int32_t* __restrict__ tcol,
                                                V* __restrict__ tval, int32_t* __restrict__ ucnt,
                                                uint32_t* __restrict__ usub) {
+  constexpr int NT = 256, PER = 4;
   __shared__ uint32_t s_key[HT];
   __shared__ unsigned long long s_lo[HT];  // sum of low 48-bit chunks
   __shared__ unsigned long long s_hi[HT];  // sum of signed high chunks
-  __shared__ uint16_t s_w[HT];     // index of the slot within its row
-  __shared__ uint16_t s_list[HT];  // slots grouped by row
+  __shared__ uint16_t s_slot[HT];  // occupied slots, in insertion order
+  __shared__ uint16_t s_w[HT];     // index of each occupied slot within its row
+  __shared__ uint16_t s_list[HT];  // occupied slots grouped by row
   __shared__ uint32_t s_rc[256];   // entries per row
   __shared__ uint32_t s_ro[256];   // row offsets
   __shared__ uint32_t s_scan[8];
-  __shared__ uint32_t s_over;
+  __shared__ uint32_t s_over, s_nu;
 
   const int64_t g = blockIdx.x;
   const uint32_t beg = sbb[g], end = sbb[g + 1];
@@ -552,44 +603,54 @@ __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* _
   const int F = 1117 - (int)*emax;
   const uint32_t cmask = (1u << colbits) - 1;
 
-  for (int h = threadIdx.x; h < HT; h += blockDim.x) {
+  for (int h = threadIdx.x; h < HT; h += NT) {
     s_key[h] = kEmptyKey;
     s_lo[h] = 0ull;
     s_hi[h] = 0ull;
   }
-  for (int r = threadIdx.x; r < (1 << s2); r += blockDim.x) s_rc[r] = 0;
+  for (int r = threadIdx.x; r < (1 << s2); r += NT) s_rc[r] = 0;
   // more than 2^16 pairs could overflow the chunk sums: take the global path
-  if (threadIdx.x == 0) s_over = (end - beg > (1u << 16)) ? 1u : 0u;
+  if (threadIdx.x == 0) {
+    s_over = (end - beg > (1u << 16)) ? 1u : 0u;
+    s_nu = 0;
+  }
   __syncthreads();
-  // stream the pairs into the table, eight per lane in flight
+  // stream the pairs into the table: PER loads per lane in flight (indices clamped into
+  // the range, so every load is issued before the first use)
   if (!s_over) {
-    for (uint32_t i0 = beg + threadIdx.x; i0 < end; i0 += 8 * 256) {
-      uint32_t kk[8];
-      double vv[8];
+    for (uint32_t i0 = beg; i0 < end; i0 += PER * NT) {
+      uint32_t kk[PER];
+      V vv[PER];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const uint32_t i = i0 + u * 256;
-        kk[u] = i < end ? ikey[i] : kEmptyKey;
-        vv[u] = i < end ? (double)ival[i] : 0.0;
+      for (int u = 0; u < PER; ++u) {
+        const uint32_t i = i0 + u * NT + threadIdx.x;
+        const uint32_t ic = i < end ? i : beg;
+        kk[u] = ikey[ic];
+        vv[u] = ival[ic];
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < PER; ++u) {
+        if (i0 + u * NT + threadIdx.x >= end) continue;
         const uint32_t key = kk[u];
-        if (key == kEmptyKey) continue;
-        uint64_t qlo, qhi;
-        to_fixed(vv[u], F, qlo, qhi);
         uint32_t h = key_hash(key) & (HT - 1);
+        uint32_t k = s_key[h];
         int probes = 0;
-        bool found = false;
-        while (probes < HT) {
-          uint32_t k = s_key[h];
-          if (k == kEmptyKey) k = atomicCAS(&s_key[h], kEmptyKey, key);
-          if (k == kEmptyKey || k == key) {
-            found = true;
+        bool found = true;
+        while (k != key) {
+          if (k == kEmptyKey) {
+            k = atomicCAS(&s_key[h], kEmptyKey, key);
+            if (k == kEmptyKey) {  // inserted: record the slot
+              s_slot[atomicAdd(&s_nu, 1u)] = (uint16_t)h;
+              break;
+            }
+            if (k == key) break;
+          }
+          if (++probes >= HT) {
+            found = false;
             break;
           }
           h = (h + 1) & (HT - 1);
-          ++probes;
+          k = s_key[h];
         }
         if (!found) {
           s_over = 1;
@@ -597,9 +658,9 @@ __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* _
         }
         uint64_t c0;
         int64_t c1;
-        split48(qlo, qhi, c0, c1);
-        if (c0) atomicAdd(&s_lo[h], (unsigned long long)c0);
-        if (c1) atomicAdd(&s_hi[h], (unsigned long long)c1);
+        to_chunks(vv[u], F, c0, c1);
+        atomicAdd(&s_lo[h], (unsigned long long)c0);
+        atomicAdd(&s_hi[h], (unsigned long long)c1);
       }
     }
   }
@@ -609,35 +670,34 @@ __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* _
       pass3_global<V>(ikey + beg, ival + beg, end - beg, r0, R, colbits, F, tcol + beg, tval + beg, ucnt, usub + g);
     return;
   }
-  // order the entries by (row, col)
-  for (int h = threadIdx.x; h < HT; h += blockDim.x) {
-    const uint32_t k = s_key[h];
-    if (k != kEmptyKey) s_w[h] = (uint16_t)atomicAdd(&s_rc[k >> colbits], 1u);
-  }
+  // order the U entries by (row, col): count per row, scan, group by row, rank by col
+  const uint32_t U = s_nu;
+  for (uint32_t f = threadIdx.x; f < U; f += NT)
+    s_w[f] = (uint16_t)atomicAdd(&s_rc[s_key[s_slot[f]] >> colbits], 1u);
   __syncthreads();
   const int RB = 1 << s2;  // rows of a full sub-bucket (<= 256)
-  for (int r = threadIdx.x; r < RB; r += blockDim.x) s_ro[r] = s_rc[r];
+  for (int r = threadIdx.x; r < RB; r += NT) s_ro[r] = s_rc[r];
   __syncthreads();
-  const uint32_t U = block_scan_array(s_ro, RB, s_scan);
-  for (int h = threadIdx.x; h < HT; h += blockDim.x) {
-    const uint32_t k = s_key[h];
-    if (k != kEmptyKey) s_list[s_ro[k >> colbits] + s_w[h]] = (uint16_t)h;
+  block_scan_array(s_ro, RB, s_scan);
+  for (uint32_t f = threadIdx.x; f < U; f += NT) {
+    const uint32_t h = s_slot[f];
+    s_list[s_ro[s_key[h] >> colbits] + s_w[f]] = (uint16_t)h;
   }
   __syncthreads();
-  for (int h = threadIdx.x; h < HT; h += blockDim.x) {
+  for (uint32_t f = threadIdx.x; f < U; f += NT) {
+    const uint32_t h = s_slot[f];
     const uint32_t k = s_key[h];
-    if (k == kEmptyKey) continue;
     const uint32_t row = k >> colbits, col = k & cmask;
     const uint32_t ro = s_ro[row], nr = s_rc[row];
     uint32_t rank = 0;
     for (uint32_t q = 0; q < nr; ++q) rank += ((s_key[s_list[ro + q]] & cmask) < col) ? 1u : 0u;
-    const uint32_t f = ro + rank;
-    tcol[beg + f] = (int32_t)col;
+    const uint32_t pos = ro + rank;
+    tcol[beg + pos] = (int32_t)col;
     uint64_t lo, hi;
     join48(s_lo[h], (int64_t)s_hi[h], lo, hi);
-    tval[beg + f] = (V)from_fixed(lo, hi, F);
+    tval[beg + pos] = (V)from_fixed(lo, hi, F);
   }
-  for (int r = threadIdx.x; r < R; r += blockDim.x) ucnt[r0 + r] = (int32_t)s_rc[r];
+  for (int r = threadIdx.x; r < R; r += NT) ucnt[r0 + r] = (int32_t)s_rc[r];
   if (threadIdx.x == 0) usub[g] = U;
 }
 

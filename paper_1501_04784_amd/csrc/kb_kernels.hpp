@@ -18,6 +18,15 @@ constexpr int kScanChunk = kScanThreads * kScanItems;
 
 __device__ __forceinline__ void raise_flag(uint32_t* status, uint32_t f) { atomicOr(status, f); }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup b runs on XCD b % 8).
+// Map b to a work item so that each XCD takes one contiguous range of the n items: the
+// runs that neighbouring items write next to each other then meet in the same L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_item(int64_t b, int64_t n) {
+  const int64_t x = b % kXcds, i = b / kXcds, full = n / kXcds, rem = n % kXcds;
+  return x * full + (x < rem ? x : rem) + i;
+}
+
 template <int NEN>
 __device__ __forceinline__ void load_conn(const int32_t* __restrict__ conn, int64_t e, int32_t (&E)[NEN]) {
 #pragma unroll
@@ -204,54 +213,45 @@ __global__ void k_pad_coords(const double* __restrict__ c, int64_t n, double4* _
     out[i] = make_double4(c[3 * i], c[3 * i + 1], c[3 * i + 2], 0.0);
 }
 
-// Integrate element e into k (value type V, c applied).  Adds flag bits to *f and
-// counts a fallback in *fb.  E must be valid.
-template <int NEN, Prec P, typename NODES>
-__device__ __forceinline__ void element_values(const NODES& nodes, const double* __restrict__ coef, int64_t e,
-                                               const int32_t (&E)[NEN], float tau,
-                                               typename PrecTraits<P>::V (&k)[ElemTraits<NEN>::T], uint32_t* f,
-                                               uint32_t* fb) {
+// Coordinates of the element's nodes, gathered once into registers.
+template <int NEN, typename NODES>
+__device__ __forceinline__ void gather_nodes(const NODES& nodes, const int32_t (&E)[NEN], double (&Xn)[NEN][3]) {
+#pragma unroll
+  for (int a = 0; a < NEN; ++a) nodes.get(E[a], Xn[a]);
+}
+
+// Integrate one element from its gathered node coordinates Xn and coefficient c into k
+// (value type V, c applied).  Adds flag bits to *f and counts a fallback in *fb.
+template <int NEN, Prec P>
+__device__ __forceinline__ void element_values_at(const double (&Xn)[NEN][3], double c, float tau,
+                                                  typename PrecTraits<P>::V (&k)[ElemTraits<NEN>::T], uint32_t* f,
+                                                  uint32_t* fb) {
   constexpr int T = ElemTraits<NEN>::T;
   using V = typename PrecTraits<P>::V;
-  double X0[3];
-  nodes.get(E[0], X0);
-  const double c = coef[e];
   bool ok;
   if constexpr (P == Prec::F64) {
     double X[NEN][3];
-    X[0][0] = X[0][1] = X[0][2] = 0.0;
 #pragma unroll
-    for (int a = 1; a < NEN; ++a) {
-      double xa[3];
-      nodes.get(E[a], xa);
+    for (int a = 0; a < NEN; ++a)
 #pragma unroll
-      for (int j = 0; j < 3; ++j) X[a][j] = xa[j] - X0[j];
-    }
+      for (int j = 0; j < 3; ++j) X[a][j] = a ? Xn[a][j] - Xn[0][j] : 0.0;
     ok = integrate<NEN, double, double, false>(X, k, 0.0, nullptr);
   } else {
     float X[NEN][3];
-    X[0][0] = X[0][1] = X[0][2] = 0.f;
 #pragma unroll
-    for (int a = 1; a < NEN; ++a) {
-      double xa[3];
-      nodes.get(E[a], xa);
+    for (int a = 0; a < NEN; ++a)
 #pragma unroll
-      for (int j = 0; j < 3; ++j) X[a][j] = (float)(xa[j] - X0[j]);
-    }
+      for (int j = 0; j < 3; ++j) X[a][j] = a ? (float)(Xn[a][j] - Xn[0][j]) : 0.f;
     bool need_fb = false;
     ok = integrate<NEN, float, float, P == Prec::F32FB>(X, k, tau, &need_fb);
     if constexpr (P == Prec::F32FB) {
       if (need_fb) {
         // Jacobian, determinant and adjugate in FP64 for this element
         double Xd[NEN][3];
-        Xd[0][0] = Xd[0][1] = Xd[0][2] = 0.0;
 #pragma unroll
-        for (int a = 1; a < NEN; ++a) {
-          double xa[3];
-          nodes.get(E[a], xa);
+        for (int a = 0; a < NEN; ++a)
 #pragma unroll
-          for (int j = 0; j < 3; ++j) Xd[a][j] = xa[j] - X0[j];
-        }
+          for (int j = 0; j < 3; ++j) Xd[a][j] = a ? Xn[a][j] - Xn[0][j] : 0.0;
         ok = integrate<NEN, double, float, false>(Xd, k, 0.0, nullptr);
         *fb += 1;
       }
@@ -265,6 +265,17 @@ __device__ __forceinline__ void element_values(const NODES& nodes, const double*
   }
   if (!ok) *f |= KB_F_INVERTED;
   if (!finite) *f |= KB_F_NONFINITE;
+}
+
+// Gather and integrate element e.  E must be valid.
+template <int NEN, Prec P, typename NODES>
+__device__ __forceinline__ void element_values(const NODES& nodes, const double* __restrict__ coef, int64_t e,
+                                               const int32_t (&E)[NEN], float tau,
+                                               typename PrecTraits<P>::V (&k)[ElemTraits<NEN>::T], uint32_t* f,
+                                               uint32_t* fb) {
+  double Xn[NEN][3];
+  gather_nodes<NEN>(nodes, E, Xn);
+  element_values_at<NEN, P>(Xn, coef[e], tau, k, f, fb);
 }
 
 template <int NEN, Prec P>
