@@ -37,9 +37,9 @@ def algorithmic_bytes(elem: int, n_elem: int, n_node: int, nnz: int, prec: str) 
     """Compulsory HBM bytes of each stage and of the whole path (per launch).
 
     Per stage: its inputs read once and its outputs written once, in the formats the
-    stage exchanges ((8-byte key, value) pairs between the partition passes).  For the
-    path: E, c and C read once (coordinates once per node), the lower values written
-    once and read once, CSR written once.
+    stages exchange: (row, col, value) after pass 1, (packed key, value) after pass 2.
+    For the path: E, c and C read once (coordinates once per node), the lower values
+    written once and read once, CSR written once.
     """
     vb = 8 if prec == "fp64" else 4
     nen = elem
@@ -50,14 +50,53 @@ def algorithmic_bytes(elem: int, n_elem: int, n_node: int, nnz: int, prec: str) 
     coords = 24 * n_node
     b = {
         "count": conn,                                            # E in (histogram out is small)
-        "integrate": conn + coef + coords + (8 + vb) * T,         # E, c, C in; (key, value) pairs out
-        "partition": 8 * T + 2 * (8 + vb) * T,                    # keys for the histogram, pairs in and out
-        "reduce": (8 + vb) * T + (4 + vb) * nnz + 4 * n_node,     # pairs in; unique entries, row counts out
+        "integrate": conn + coef + coords + (8 + vb) * T,         # E, c, C in; (row, col, value) out
+        "histogram": 4 * T,                                       # rows in (histograms out are small)
+        "partition": (8 + vb) * T + (4 + vb) * T,                 # (row, col, value) in, (key, value) out
+        "reduce": (4 + vb) * T + (4 + vb) * nnz + 4 * n_node,     # pairs in; unique entries, row counts out
         "compress": 2 * (4 + vb) * nnz + 8 * n_node,              # unique entries in, CSR out
     }
     # the path as a whole: E, c, C in once, lower values once out and in, CSR out
     b["path"] = conn + coef + coords + 2 * vb * T + (4 + vb) * nnz + 4 * (n_node + 1)
     return b
+
+
+# stages that are exactly one kernel: the roofline is reported for the slowest of them
+SINGLE_KERNEL_STAGES = {"integrate": "k_pass1", "partition": "k_scatter2", "reduce": "k_pass3"}
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+SOURCE_DIR = os.path.join(ROOT, "paper_1501_04784_amd", "csrc")
+
+
+def source_digest() -> str:
+    """sha256 over the HIP sources, to tell whether stored counters still apply."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(SOURCE_DIR)):
+        with open(os.path.join(SOURCE_DIR, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def stored_traffic(kernel: str, workload: str, prec: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary, if it was
+    taken on the current sources (else None).  The summary holds lines
+    `traffic_bytes: N` and `source_sha256: H`."""
+    path = os.path.join(PROFILE_DIR, f"counters_{workload}_{prec}.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and line.strip().startswith(("traffic_bytes", "source_sha256")):
+            k, v = line.strip().split(":", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    sec = [l for l in open(path).read().split("\n## ") if l.startswith(kernel)]
+    if not sec or fields.get("source_sha256") != source_digest():
+        return None
+    for line in sec[0].splitlines():
+        if line.strip().startswith("traffic_bytes:"):
+            return float(line.split(":", 1)[1])
+    return None
 
 
 def parse():
@@ -173,10 +212,13 @@ def main():
         "path_hbm_frac": ab["path"] / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
     }
     if stages:
-        dom = max((k for k in stages if k in ab), key=lambda k: stages[k])
+        dom = max(SINGLE_KERNEL_STAGES, key=lambda k: stages[k])
+        kernel = SINGLE_KERNEL_STAGES[dom] + ("_tet" if dom == "integrate" and m.elem == 4 else "")
         achieved = ab[dom] / (stages[dom] * 1e-3) / 1e9
-        out["roofline"] = {"bound": "hbm", "kernel_stage": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None}
+        out["roofline"] = {"bound": "hbm", "kernel": kernel, "stage": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                           "traffic": stored_traffic(kernel, args.workload, prec),
+                           "kernel_ms": stages[dom], "algorithmic_bytes": ab[dom]}
         out["stages_ms"] = stages
     if not args.no_fp64 and prec != "fp64":
         ms64, _, st64, r64 = time_builds(kb, torch, mesh_dev, m, "fp64", max(3, args.steps // 2), 2,

@@ -87,14 +87,16 @@ extern "C" {
  * status_dev[2], status_dev[3]: reserved, written as 0 */
 
 /* stages recorded into kb_tuning.stage_events (KB_N_STAGES + 1 events) */
-#define KB_N_STAGES 7
-#define KB_STAGE_INIT 0       /* clear status                                             */
-#define KB_STAGE_COUNT 1      /* validate connectivity, pairs per row bucket per tile      */
-#define KB_STAGE_OFFSETS 2    /* scan: each tile's write offset in each bucket             */
-#define KB_STAGE_INTEGRATE 3  /* integrate (or read given values), partition by bucket    */
-#define KB_STAGE_PARTITION 4  /* partition each bucket into sub-buckets                    */
-#define KB_STAGE_REDUCE 5     /* per sub-bucket: group equal (row, col), ordered FP64 sums */
-#define KB_STAGE_COMPRESS 6   /* scan of unique counts, row_ptr, col_idx / vals            */
+#define KB_N_STAGES 8
+#define KB_STAGE_INIT 0       /* clear status                                              */
+#define KB_STAGE_COUNT 1      /* validate connectivity, pairs per row bucket per tile       */
+#define KB_STAGE_OFFSETS 2    /* scan: each tile's write offset in each bucket; coordinates
+                                 copied into padded 32-byte records                        */
+#define KB_STAGE_INTEGRATE 3  /* integrate (or read given values), partition by bucket     */
+#define KB_STAGE_HISTOGRAM 4  /* sub-bucket histogram per segment of a bucket, offsets      */
+#define KB_STAGE_PARTITION 5  /* partition each bucket into sub-buckets                     */
+#define KB_STAGE_REDUCE 6     /* per sub-bucket: group equal (row, col), exact sums         */
+#define KB_STAGE_COMPRESS 7   /* scan of unique counts, row_ptr, col_idx / vals             */
 
 typedef struct {
   int32_t elem;          /* KB_HEX8 or KB_TET4                                         */

@@ -12,8 +12,8 @@ KB_FP64, KB_FP32, KB_FP32_FB64 = 0, 1, 2
 KB_OK, KB_EINVAL, KB_ERANGE, KB_ENOSPC, KB_EHIP = 0, -1, -2, -3, -4
 KB_STATUS_WORDS = 4
 KB_F_INDEX, KB_F_REPEAT, KB_F_INVERTED, KB_F_NONFINITE, KB_F_CAPACITY = 1, 2, 4, 8, 16
-KB_N_STAGES = 7
-STAGE_NAMES = ("init", "count", "offsets", "integrate", "partition", "reduce", "compress")
+KB_N_STAGES = 8
+STAGE_NAMES = ("init", "count", "offsets", "integrate", "histogram", "partition", "reduce", "compress")
 
 # every function declared in include/kbuild.h
 EXPORTS = ("kb_plan", "kb_build_lower_csr", "kb_integrate_lower", "kb_assemble_lower_csr", "kb_status_string",

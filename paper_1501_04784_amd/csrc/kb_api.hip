@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 
 #include "kb_assemble.hpp"
 #include "kb_kernels.hpp"
@@ -38,13 +39,33 @@ struct Plan {
   int colbits = 1;                     // bits of a column index
   int ht = 2048;                       // pass-3 hash slots
   int tile = 0;                        // elements (= threads) per pass-1 workgroup
+  int cus = 256;                       // compute units of the current device (launch time)
   int64_t ntiles = 0, nsub = 0, nhist = 0, nseg_max = 0;
   size_t lds1 = 0, lds2 = 0;
   // workspace offsets
-  size_t o_coords4 = 0, o_hist = 0, o_histT = 0, o_part = 0, o_total = 0, o_bstart = 0, o_segbase = 0, o_hist2 = 0, o_emax = 0,
-         o_row1 = 0, o_col1 = 0, o_val1 = 0, o_key2 = 0, o_val2 = 0, o_sbb = 0, o_ucnt = 0, o_usub = 0, o_ubase = 0,
+  size_t o_coords4 = 0, o_hist = 0, o_histT = 0, o_part = 0, o_total = 0, o_bstart = 0, o_segbase = 0, o_hist2 = 0, o_seg2b = 0, o_emax = 0,
+         o_row1 = 0, o_col1 = 0, o_val1 = 0, o_key2 = 0, o_val2 = 0, o_sbb = 0, o_rowoff = 0, o_usub = 0, o_ubase = 0,
          total = 0;
 };
+
+// compute units of the current device, cached per device ordinal
+int device_cus(int* out) {
+  static std::atomic<int> cache[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return KB_EHIP;
+  if (dev >= 0 && dev < 64) {
+    const int c = cache[dev].load(std::memory_order_relaxed);
+    if (c > 0) {
+      *out = c;
+      return KB_OK;
+    }
+  }
+  int n = 0;
+  if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) return KB_EHIP;
+  if (dev >= 0 && dev < 64) cache[dev].store(n, std::memory_order_relaxed);
+  *out = n;
+  return KB_OK;
+}
 
 int ilog2_ceil(int64_t x) {
   int k = 0;
@@ -123,8 +144,8 @@ int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p) {
   p->ntiles = div_up(p->nel, p->tile);
   p->nhist = (int64_t)p->nb * p->ntiles;
   p->nseg_max = div_up(p->T, kSeg) + p->nb;
-  p->lds1 = (size_t)p->tile * p->te * (8 + p->vbytes) + 3 * 4 * (size_t)p->nb + 4 * (p->tile / 64 + 2);
-  p->lds2 = (size_t)kSeg * (p->vbytes + 4 + 2) + 3 * 4 * (size_t)p->p2 + 4 * (kSegThreads / 64 + 1);
+  p->lds1 = (size_t)p->tile * p->te * (8 + p->vbytes) + 2 * 4 * (size_t)p->nb + 4 * (p->tile / 64 + 2);
+  p->lds2 = (size_t)kSeg * (p->vbytes + 4 + 2) + 2 * 4 * (size_t)p->p2 + 4 * (kSegThreads / 64 + 1);
   if (p->lds1 > 163840 || p->lds2 > 163840) return KB_EINVAL;
   size_t off = 0;
   auto take = [&](size_t bytes) {  // every region at least one aligned block
@@ -133,7 +154,7 @@ int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p) {
     return o;
   };
   const size_t T = (size_t)p->T;
-  const int64_t scan_n = std::max(std::max(p->nhist, p->nseg_max * p->p2), p->nsub + 1);
+  const int64_t scan_n = std::max(p->nhist, p->nsub + 1);
   p->o_coords4 = take(32 * (size_t)p->nn);
   // scan outputs hold n + 1 words: the scan writes its total after the last entry
   p->o_hist = take(4 * (size_t)p->nhist);
@@ -142,7 +163,8 @@ int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p) {
   p->o_total = take(8);
   p->o_bstart = take(4 * ((size_t)p->nb + 1));
   p->o_segbase = take(4 * ((size_t)p->nb + 1));
-  p->o_hist2 = take(4 * ((size_t)(p->nseg_max * p->p2) + 1));
+  p->o_hist2 = take(4 * (size_t)(p->nseg_max * p->p2));
+  p->o_seg2b = take(4 * (size_t)p->nseg_max);
   p->o_emax = take(4);
   p->o_row1 = take(4 * T);
   p->o_col1 = take(4 * T);
@@ -150,7 +172,7 @@ int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p) {
   p->o_key2 = take(4 * T);
   p->o_val2 = take(p->vbytes * T);
   p->o_sbb = take(4 * ((size_t)p->nsub + 1));
-  p->o_ucnt = take(4 * (size_t)p->nn);
+  p->o_rowoff = take(4 * (size_t)p->nn);
   p->o_usub = take(4 * ((size_t)p->nsub + 1));
   p->o_ubase = take(4 * ((size_t)p->nsub + 1));
   p->total = off;
@@ -214,13 +236,23 @@ template <int NEN, Prec P, bool FROM_VALUES, int BLOCK>
 int launch_pass1_block(const Plan& p, const kb_mesh* m, const void* klow, unsigned char* ws, uint32_t* status,
                        hipStream_t s) {
   using V = typename PrecTraits<P>::V;
-  auto kern = k_pass1<NEN, P, FROM_VALUES, BLOCK>;
+  auto kern = [] {
+    if constexpr (NEN == 4)
+      return k_pass1_tet<P, FROM_VALUES, BLOCK>;
+    else
+      return k_pass1<NEN, P, FROM_VALUES, BLOCK>;
+  }();
   if (!set_lds(kern, p.lds1)) return KB_EHIP;
-  kern<<<(unsigned)p.ntiles, BLOCK, p.lds1, s>>>(m->conn, (const double4*)(ws + p.o_coords4), m->coef, (const V*)klow,
-                                                p.nel, p.nn, p.tau,
-                                                p.s1, p.nb, (const uint32_t*)(ws + p.o_hist),
-                                                (uint32_t*)(ws + p.o_row1), (uint32_t*)(ws + p.o_col1),
-                                                (V*)(ws + p.o_val1), (uint32_t*)(ws + p.o_emax), status);
+  // tetrahedra: persistent, the workgroups that fit on the device at once (LDS-bound),
+  // at least one per XCD slot (b % 8) that owns tiles; bricks: one tile per workgroup
+  const int per_cu = std::max(1, (int)(163840 / std::max<size_t>(p.lds1, 1)));
+  const int64_t g1 =
+      NEN == 8 ? p.ntiles
+               : std::min<int64_t>(p.ntiles, std::max<int64_t>(8, (int64_t)p.cus * std::min(per_cu, 2048 / BLOCK)));
+  kern<<<(unsigned)g1, BLOCK, p.lds1, s>>>(m->conn, (const double4*)(ws + p.o_coords4), m->coef, (const V*)klow, p.nel,
+                                           p.nn, p.tau, p.s1, p.nb, p.ntiles, (const uint32_t*)(ws + p.o_hist),
+                                           (uint32_t*)(ws + p.o_row1), (uint32_t*)(ws + p.o_col1),
+                                           (V*)(ws + p.o_val1), (uint32_t*)(ws + p.o_emax), status);
   KB_LAUNCH_CHECK();
   return KB_OK;
 }
@@ -249,6 +281,7 @@ int assemble_tail(const Plan& p, unsigned char* ws, int32_t* row_ptr, int32_t* c
   auto* bstart = (uint32_t*)(ws + p.o_bstart);
   auto* segbase = (uint32_t*)(ws + p.o_segbase);
   auto* hist2 = (uint32_t*)(ws + p.o_hist2);
+  auto* seg2b = (uint32_t*)(ws + p.o_seg2b);
   auto* emax = (uint32_t*)(ws + p.o_emax);
   auto* row1 = (uint32_t*)(ws + p.o_row1);
   auto* col1 = (uint32_t*)(ws + p.o_col1);
@@ -256,25 +289,30 @@ int assemble_tail(const Plan& p, unsigned char* ws, int32_t* row_ptr, int32_t* c
   auto* key2 = (uint32_t*)(ws + p.o_key2);
   auto* val2 = (V*)(ws + p.o_val2);
   auto* sbb = (uint32_t*)(ws + p.o_sbb);
-  auto* ucnt = (int32_t*)(ws + p.o_ucnt);
+  auto* rowoff = (uint32_t*)(ws + p.o_rowoff);
   auto* usub = (uint32_t*)(ws + p.o_usub);
   auto* ubase = (uint32_t*)(ws + p.o_ubase);
   auto* part = (int32_t*)(ws + p.o_part);
   // pass-3 output reuses the pass-1 buffers (dead after pass 2)
   auto* tcol = (int32_t*)row1;
   auto* tval = val1;
+  KB_TRY(ev.rec(KB_STAGE_HISTOGRAM));
+  if (p.nb > 0) {
+    const unsigned gs = (unsigned)p.nseg_max;
+    k_seg_map<<<(unsigned)p.nb, 256, 0, s>>>(segbase, seg2b);
+    KB_LAUNCH_CHECK();
+    k_hist2<kSeg><<<gs, 256, 4 * (size_t)p.p2, s>>>(row1, bstart, segbase, seg2b, p.nb, p.s2, p.p2, hist2);
+    KB_LAUNCH_CHECK();
+    k_colscan<<<(unsigned)p.nb, 256, 0, s>>>(hist2, bstart, segbase, p.nb, p.p2, sbb);
+    KB_LAUNCH_CHECK();
+  }
   KB_TRY(ev.rec(KB_STAGE_PARTITION));
   if (p.nb > 0) {
     const unsigned gs = (unsigned)p.nseg_max;
-    k_hist2<kSeg><<<gs, 256, 4 * (size_t)p.p2, s>>>(row1, bstart, segbase, p.nb, p.s2, p.p2, hist2);
-    KB_LAUNCH_CHECK();
-    KB_TRY(scan((const int32_t*)hist2, p.nseg_max * p.p2, part, (int32_t*)hist2, nullptr, s));
-    k_subbucket_starts<<<grid_for(p.nsub + 1, 256), 256, 0, s>>>(hist2, bstart, segbase, p.nb, p.p2, sbb);
-    KB_LAUNCH_CHECK();
     auto k2 = k_scatter2<V, kSeg, kSegThreads>;
     if (!set_lds(k2, p.lds2)) return KB_EHIP;
-    k2<<<gs, kSegThreads, p.lds2, s>>>(row1, col1, val1, bstart, segbase, hist2, p.nb, p.s2, p.p2, p.colbits, key2,
-                                      val2);
+    k2<<<gs, kSegThreads, p.lds2, s>>>(row1, col1, val1, bstart, segbase, seg2b, hist2, sbb, p.nb, p.s2, p.p2,
+                                      p.colbits, key2, val2);
     KB_LAUNCH_CHECK();
   }
   KB_TRY(ev.rec(KB_STAGE_REDUCE));
@@ -282,16 +320,20 @@ int assemble_tail(const Plan& p, unsigned char* ws, int32_t* row_ptr, int32_t* c
     const unsigned g3 = (unsigned)p.nsub;
     switch (p.ht) {
       case 512:
-        k_pass3<V, 512><<<g3, 256, 0, s>>>(key2, val2, sbb, p.s2, p.colbits, p.nn, emax, tcol, tval, ucnt, usub);
+        k_pass3<V, 512><<<g3, 256, 0, s>>>(key2, val2, sbb, p.s2, p.colbits, p.nn, emax, tcol, tval, rowoff,
+                                           usub);
         break;
       case 1024:
-        k_pass3<V, 1024><<<g3, 256, 0, s>>>(key2, val2, sbb, p.s2, p.colbits, p.nn, emax, tcol, tval, ucnt, usub);
+        k_pass3<V, 1024><<<g3, 256, 0, s>>>(key2, val2, sbb, p.s2, p.colbits, p.nn, emax, tcol, tval, rowoff,
+                                            usub);
         break;
       case 2048:
-        k_pass3<V, 2048><<<g3, 256, 0, s>>>(key2, val2, sbb, p.s2, p.colbits, p.nn, emax, tcol, tval, ucnt, usub);
+        k_pass3<V, 2048><<<g3, 256, 0, s>>>(key2, val2, sbb, p.s2, p.colbits, p.nn, emax, tcol, tval, rowoff,
+                                            usub);
         break;
       default:
-        k_pass3<V, 4096><<<g3, 256, 0, s>>>(key2, val2, sbb, p.s2, p.colbits, p.nn, emax, tcol, tval, ucnt, usub);
+        k_pass3<V, 4096><<<g3, 256, 0, s>>>(key2, val2, sbb, p.s2, p.colbits, p.nn, emax, tcol, tval, rowoff,
+                                            usub);
         break;
     }
     KB_LAUNCH_CHECK();
@@ -299,8 +341,8 @@ int assemble_tail(const Plan& p, unsigned char* ws, int32_t* row_ptr, int32_t* c
   KB_TRY(ev.rec(KB_STAGE_COMPRESS));
   KB_TRY(scan((const int32_t*)usub, p.nsub, part, (int32_t*)ubase, nnz_dev, s));
   if (p.nsub > 0) {
-    k_final<V><<<(unsigned)p.nsub, 256, 0, s>>>(sbb, ubase, tcol, tval, ucnt, p.s2, p.nn, p.nsub, row_ptr, col_idx,
-                                                vals, cap, status);
+    k_final<V><<<(unsigned)div_up(p.nsub, 4), 256, 0, s>>>(sbb, ubase, tcol, tval, rowoff, p.s2, p.nn, p.nsub, row_ptr,
+                                                           col_idx, vals, cap, status);
     KB_LAUNCH_CHECK();
   } else {
     k_scan_empty<<<1, 1, 0, s>>>(row_ptr, nullptr);
@@ -346,13 +388,14 @@ int build_impl(const Plan& p, const kb_mesh* m, const void* klow, unsigned char*
     k_segments<<<1, 256, 0, s>>>(bstart, p.nb, kSeg, segbase);
     KB_LAUNCH_CHECK();
   }
+  if (p.ntiles > 0 && p.nb > 0 && !klow && p.nn > 0) {
+    k_pad_coords<<<(unsigned)std::min<int64_t>(div_up(p.nn, 256), 8192), 256, 0, s>>>(m->coords, p.nn,
+                                                                                     (double4*)(ws + p.o_coords4));
+    KB_LAUNCH_CHECK();
+  }
+  // the integrate stage is exactly one kernel (pass 1)
   KB_TRY(ev.rec(KB_STAGE_INTEGRATE));
   if (p.ntiles > 0 && p.nb > 0) {
-    if (!klow && p.nn > 0) {
-      k_pad_coords<<<(unsigned)std::min<int64_t>(div_up(p.nn, 256), 8192), 256, 0, s>>>(
-          m->coords, p.nn, (double4*)(ws + p.o_coords4));
-      KB_LAUNCH_CHECK();
-    }
     if (klow) {
       KB_TRY((launch_pass1<NEN, P, true>(p, m, klow, ws, status, s)));
     } else {
@@ -388,7 +431,7 @@ int integrate_impl(const Plan& p, const kb_mesh* m, void* vals, uint32_t* status
                                                                           p.tau, (V*)vals, status);
     KB_LAUNCH_CHECK();
   }
-  for (int i = KB_STAGE_PARTITION; i <= KB_N_STAGES; ++i) KB_TRY(ev.rec(i));
+  for (int i = KB_STAGE_HISTOGRAM; i <= KB_N_STAGES; ++i) KB_TRY(ev.rec(i));
   return KB_OK;
 }
 
@@ -450,6 +493,7 @@ static int build_common(const kb_mesh* mesh, int prec, const kb_tuning* tuning, 
   if (cap > 0 && (!col_idx || !vals)) return KB_EINVAL;
   if (ws_bytes < p.total) return KB_ENOSPC;
   if (p.total > 0 && !ws) return KB_EINVAL;
+  KB_TRY(device_cus(&p.cus));
   Events ev{tuning ? tuning->stage_events : nullptr, (hipStream_t)stream};
   auto* w = (unsigned char*)ws;
   auto s = (hipStream_t)stream;

@@ -14,8 +14,9 @@
 //            at the tile's offset as (row, col, value) arrays.  Also the largest value
 //            exponent, which fixes the exact-sum scale below.
 //   pass 2   per fixed-size segment of a bucket: histogram of sub-buckets
-//            (row >> s2), global scan, then LDS-staged scatter into contiguous
-//            sub-bucket ranges; pairs are repacked as (row_local << colbits | col, value).
+//            (row >> s2); per bucket, a prefix over its segments for each sub-bucket;
+//            then LDS-staged scatter into contiguous sub-bucket ranges; pairs are
+//            repacked as (row_local << colbits | col, value).
 //   pass 3   per sub-bucket: stream its pairs into an LDS hash table keyed by the
 //            packed (row, col); each value is added as a 128-bit fixed-point integer
 //            (scale 2^F from the largest exponent), so every sum is exact and its
@@ -139,10 +140,14 @@ __device__ __forceinline__ void split48(uint64_t lo, uint64_t hi, uint64_t& c0, 
 // Same truncation toward zero as to_fixed; no branches.
 __device__ __forceinline__ void chunks_from_mag(uint64_t m, int sh, bool neg, uint64_t& c0, int64_t& c1) {
   constexpr uint64_t M48 = (1ull << 48) - 1;
-  const uint64_t mag = sh >= 0 ? (sh < 64 ? m << sh : 0ull) : (-sh < 64 ? m >> -sh : 0ull);
+  // both shift directions are formed and one is selected (64-bit shifts use the
+  // amount mod 64, so out-of-range amounts are masked to zero explicitly)
+  const uint64_t ml = m << (sh & 63), mr = m >> (-sh & 63);
+  const uint64_t mag = sh >= 0 ? (sh < 64 ? ml : 0ull) : (sh > -64 ? mr : 0ull);
   const uint64_t lo = mag & M48;  // low 48 bits of the (truncated) magnitude
   const int hs = 48 - sh;         // m >> hs is the magnitude above bit 48
-  const uint64_t hi = hs <= 0 ? m << -hs : (hs < 64 ? m >> hs : 0ull);
+  const uint64_t hl = m << (-hs & 63), hr = m >> (hs & 63);
+  const uint64_t hi = hs <= 0 ? hl : (hs < 64 ? hr : 0ull);
   const uint64_t borrow = lo ? 1ull : 0ull;
   c0 = neg ? ((1ull << 48) - lo) & M48 : lo;
   c1 = neg ? -(int64_t)(hi + borrow) : (int64_t)hi;
@@ -270,34 +275,120 @@ __global__ __launch_bounds__(256) void k_segments(const uint32_t* __restrict__ b
 }
 
 // ------------------------------------------------------------------------ pass 1
-// Per tile of BLOCK elements (one per lane): produce the element's lower pairs, group
-// them by bucket in LDS, write runs to (orow, ocol, oval).
+// A tile is BLOCK elements, one per lane.  Its pairs are grouped by bucket (row >> s1)
+// in LDS and each bucket's run is written at the tile's offset in that bucket.
+template <typename V, int BLOCK>
+struct Pass1Smem {
+  uint64_t* key;  // [cap] staged (row << 32 | col)
+  V* val;         // [cap] staged values
+  uint32_t* cnt;  // [nb] pairs per bucket, then local run starts
+  uint32_t* base; // [nb] global offset of this tile in bucket b
+  uint32_t* scan; // [BLOCK/64 + 1]
+  uint32_t* emax; // [1]
+  __device__ Pass1Smem(unsigned char* smem, int cap, int nb) {
+    key = (uint64_t*)smem;
+    val = (V*)(key + cap);
+    cnt = (uint32_t*)(val + cap);
+    base = cnt + nb;
+    scan = base + nb;
+    emax = scan + (BLOCK / 64 + 1);
+  }
+};
+
+// count the tile's pairs per bucket, keeping each (element, row) group's offset
+// within its bucket in q; then scan: sm.cnt = local run starts.  Returns the tile's
+// pair count.  Block-wide (barriers).
+template <int NEN, typename SM>
+__device__ __forceinline__ uint32_t pass1_count(const SM& sm, const int32_t (&E)[NEN], const int (&r)[NEN], bool valid,
+                                                int s1, int nb, uint32_t (&q)[NEN]) {
+  if (valid) {
+#pragma unroll
+    for (int a = 0; a < NEN; ++a) q[a] = atomicAdd(&sm.cnt[E[a] >> s1], (uint32_t)(r[a] + 1));
+  }
+  __syncthreads();
+  return block_scan_array(sm.cnt, nb, sm.scan);
+}
+
+// stage one element's pairs: the r+1 pairs of row E[a] go contiguously into its bucket
+template <int NEN, typename V, typename SM>
+__device__ __forceinline__ void pass1_stage(const SM& sm, const int32_t (&E)[NEN], const uint32_t (&q)[NEN],
+                                            const V (&k)[ElemTraits<NEN>::T], int s1) {
+#pragma unroll
+  for (int a = 0; a < NEN; ++a) {
+    uint32_t pos = sm.cnt[E[a] >> s1] + q[a];
+    const uint64_t rk = (uint64_t)(uint32_t)E[a] << 32;
+#pragma unroll
+    for (int b = 0; b < NEN; ++b) {
+      if (E[b] <= E[a]) {
+        sm.key[pos] = rk | (uint32_t)E[b];
+        sm.val[pos] = (a >= b) ? k[lidx(a, b)] : k[lidx(b, a)];
+        ++pos;
+      }
+    }
+  }
+}
+
+// write the staged pairs: index i lies in bucket b = row >> s1, local start sm.cnt[b]
+template <typename V, typename SM>
+__device__ __forceinline__ void pass1_write(const SM& sm, uint32_t n_items, int s1, int nthreads,
+                                            uint32_t* __restrict__ orow, uint32_t* __restrict__ ocol,
+                                            V* __restrict__ oval) {
+  for (uint32_t i = threadIdx.x; i < n_items; i += nthreads) {
+    const uint64_t key = sm.key[i];
+    const uint32_t row = (uint32_t)(key >> 32);
+    const int b = (int)(row >> s1);
+    const uint32_t g = sm.base[b] + (i - sm.cnt[b]);
+    orow[g] = row;
+    ocol[g] = (uint32_t)key;
+    oval[g] = sm.val[i];
+  }
+}
+
+// largest finite biased exponent of an element's values
+template <int T, typename V>
+__device__ __forceinline__ uint32_t values_emax(const V (&k)[T]) {
+  uint32_t m = 0;
+#pragma unroll
+  for (int p = 0; p < T; ++p) {
+    const uint32_t ep = (uint32_t)biased_exponent((double)k[p]);
+    m = (ep > m && ep < 0x7FF) ? ep : m;
+  }
+  return m;
+}
+
+// element values from given per-element lower triangles (assembly-only path)
+template <int T, typename V>
+__device__ __forceinline__ void read_values(const V* __restrict__ klow, int64_t e, V (&k)[T], uint32_t* flags) {
+  bool finite = true;
+#pragma unroll
+  for (int p = 0; p < T; ++p) {
+    k[p] = klow[e * T + p];
+    finite = finite && isfinite((double)k[p]);
+  }
+  if (!finite) *flags |= KB_F_NONFINITE;
+}
+
+// Bricks: one tile per workgroup; tiles are assigned XCD-contiguously, so the runs that
+// neighbouring tiles write side by side meet in one L2.
 template <int NEN, Prec P, bool FROM_VALUES, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_pass1(const int32_t* __restrict__ conn, const double4* __restrict__ coords4,
                                                const double* __restrict__ coef,
                                                const typename PrecTraits<P>::V* __restrict__ klow, int64_t n_elem,
-                                               int64_t n_node, float tau, int s1, int nb,
+                                               int64_t n_node, float tau, int s1, int nb, int64_t ntiles,
                                                const uint32_t* __restrict__ off1, uint32_t* __restrict__ orow,
                                                uint32_t* __restrict__ ocol, typename PrecTraits<P>::V* __restrict__ oval,
                                                uint32_t* __restrict__ emax, uint32_t* __restrict__ status) {
   using V = typename PrecTraits<P>::V;
   constexpr int T = ElemTraits<NEN>::T;
-  constexpr int CAP = BLOCK * T;
   extern __shared__ __align__(16) unsigned char smem[];
-  uint64_t* s_key = (uint64_t*)smem;            // [CAP]
-  V* s_val = (V*)(s_key + CAP);                  // [CAP]
-  uint32_t* s_cnt = (uint32_t*)(s_val + CAP);    // [nb]
-  uint32_t* s_base = s_cnt + nb;                 // [nb] global offset of this tile in bucket b
-  uint32_t* s_cur = s_base + nb;                 // [nb] staging cursor
-  uint32_t* s_scan = s_cur + nb;                 // [BLOCK/64 + 1]
-  uint32_t* s_emax = s_scan + (BLOCK / 64 + 1);  // [1]
-
+  const Pass1Smem<V, BLOCK> sm(smem, BLOCK * T, nb);
   const int64_t t = xcd_item(blockIdx.x, gridDim.x);
   for (int b = threadIdx.x; b < nb; b += BLOCK) {
-    s_cnt[b] = 0;
-    s_base[b] = off1[t * nb + b];
+    sm.cnt[b] = 0;
+    sm.base[b] = off1[t * nb + b];
   }
-  if (threadIdx.x == 0) *s_emax = 0;
+  if (threadIdx.x == 0) *sm.emax = 0;
+  __syncthreads();
   const int64_t e = t * BLOCK + threadIdx.x;
   int32_t E[NEN];
   bool valid = false;
@@ -305,137 +396,186 @@ __global__ __launch_bounds__(BLOCK) void k_pass1(const int32_t* __restrict__ con
     load_conn<NEN>(conn, e, E);
     valid = check_conn<NEN>(E, n_node) == 0;
   }
-  // tetrahedra: issue the coordinate gathers now, so that their latency hides behind
-  // the counting and scan below (bricks keep their larger node set out of the
-  // registers until it is needed)
-  constexpr bool kEarly = NEN == 4 && !FROM_VALUES;
-  double Xn[kEarly ? NEN : 1][3];
-  double c_e = 0.0;
-  if constexpr (kEarly) {
-    if (valid) {
-      gather_nodes<NEN>(NodesPadded{coords4}, E, Xn);
-      c_e = coef[e];
-    }
-  }
-  __syncthreads();
   int r[NEN];
-  if (valid) {
-    node_ranks<NEN>(E, r);
-#pragma unroll
-    for (int a = 0; a < NEN; ++a) atomicAdd(&s_cnt[E[a] >> s1], (uint32_t)(r[a] + 1));
-  }
-  __syncthreads();
-  for (int b = threadIdx.x; b < nb; b += BLOCK) s_cur[b] = s_cnt[b];
-  __syncthreads();
-  const uint32_t n_items = block_scan_array(s_cur, nb, s_scan);  // s_cur = local starts
-  for (int b = threadIdx.x; b < nb; b += BLOCK) s_cnt[b] = s_cur[b];  // s_cnt = local starts (kept)
-  __syncthreads();
+  uint32_t q[NEN];
+  if (valid) node_ranks<NEN>(E, r);
+  const uint32_t n_items = pass1_count<NEN>(sm, E, r, valid, s1, nb, q);
   uint32_t flags = 0, fb = 0;
   if (valid) {
     V k[T];
-    if constexpr (FROM_VALUES) {
-      bool finite = true;
-#pragma unroll
-      for (int p = 0; p < T; ++p) {
-        k[p] = klow[e * T + p];
-        finite = finite && isfinite((double)k[p]);
-      }
-      if (!finite) flags |= KB_F_NONFINITE;
-    } else if constexpr (kEarly) {
-      element_values_at<NEN, P>(Xn, c_e, tau, k, &flags, &fb);
-    } else {
+    if constexpr (FROM_VALUES)
+      read_values<T>(klow, e, k, &flags);
+    else
       element_values<NEN, P>(NodesPadded{coords4}, coef, e, E, tau, k, &flags, &fb);
-    }
-    int em = 0;
-#pragma unroll
-    for (int p = 0; p < T; ++p) {
-      const int ep = biased_exponent((double)k[p]);
-      em = (ep > em && ep < 0x7FF) ? ep : em;
-    }
-    atomicMax(s_emax, (uint32_t)em);
-#pragma unroll
-    for (int a = 0; a < NEN; ++a) {
-      // the r+1 pairs of row E[a] are staged contiguously
-      uint32_t pos = atomicAdd(&s_cur[E[a] >> s1], (uint32_t)(r[a] + 1));
-      const uint64_t hi = (uint64_t)(uint32_t)E[a] << 32;
-#pragma unroll
-      for (int b = 0; b < NEN; ++b) {
-        if (E[b] <= E[a]) {
-          s_key[pos] = hi | (uint32_t)E[b];
-          s_val[pos] = (a >= b) ? k[lidx(a, b)] : k[lidx(b, a)];
-          ++pos;
-        }
-      }
-    }
+    atomicMax(sm.emax, values_emax<T>(k));
+    pass1_stage<NEN>(sm, E, q, k, s1);
   }
   if (flags) raise_flag(status, flags);
   if (fb) atomicAdd(&status[1], fb);
   __syncthreads();
-  if (threadIdx.x == 0 && *s_emax) atomicMax(emax, *s_emax);
-  // write runs: staged index i lies in bucket b = row >> s1, local start s_cnt[b]
-  for (uint32_t i = threadIdx.x; i < n_items; i += BLOCK) {
-    const uint64_t key = s_key[i];
-    const uint32_t row = (uint32_t)(key >> 32);
-    const int b = (int)(row >> s1);
-    const uint32_t g = s_base[b] + (i - s_cnt[b]);
-    orow[g] = row;
-    ocol[g] = (uint32_t)key;
-    oval[g] = s_val[i];
+  if (threadIdx.x == 0 && *sm.emax) atomicMax(emax, *sm.emax);
+  pass1_write(sm, n_items, s1, BLOCK, orow, ocol, oval);
+}
+
+// Tetrahedra: persistent workgroups.  XCD x owns one contiguous range of tiles and its
+// workgroups walk it interleaved (neighbouring runs again meet in one L2).  The next
+// tile's connectivity is loaded while the current tile is integrated, and its node
+// coordinates while the current tile is written.
+template <Prec P, bool FROM_VALUES, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_pass1_tet(const int32_t* __restrict__ conn,
+                                                   const double4* __restrict__ coords4,
+                                                   const double* __restrict__ coef,
+                                                   const typename PrecTraits<P>::V* __restrict__ klow, int64_t n_elem,
+                                                   int64_t n_node, float tau, int s1, int nb, int64_t ntiles,
+                                                   const uint32_t* __restrict__ off1, uint32_t* __restrict__ orow,
+                                                   uint32_t* __restrict__ ocol,
+                                                   typename PrecTraits<P>::V* __restrict__ oval,
+                                                   uint32_t* __restrict__ emax, uint32_t* __restrict__ status) {
+  using V = typename PrecTraits<P>::V;
+  constexpr int NEN = 4, T = ElemTraits<NEN>::T;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const Pass1Smem<V, BLOCK> sm(smem, BLOCK * T, nb);
+  const int64_t G = gridDim.x, x = blockIdx.x % kXcds, w = blockIdx.x / kXcds;
+  const int64_t nw = G / kXcds + (x < G % kXcds ? 1 : 0);
+  const int64_t lo = x * (ntiles / kXcds) + min(x, ntiles % kXcds);
+  const int64_t hi = lo + ntiles / kXcds + (x < ntiles % kXcds ? 1 : 0);
+  int64_t t = lo + w;
+  if (t >= hi) return;
+  if (threadIdx.x == 0) *sm.emax = 0;
+
+  auto fetch = [&](int64_t tt, int32_t (&Ef)[NEN]) {
+    const int64_t e = tt * BLOCK + threadIdx.x;
+    if (tt < hi && e < n_elem) {
+      load_conn<NEN>(conn, e, Ef);
+      return check_conn<NEN>(Ef, n_node) == 0;
+    }
+    return false;
+  };
+  int32_t E[NEN];
+  bool valid = fetch(t, E);
+  double Xn[NEN][3];
+  double c_e = 0.0;
+  if constexpr (!FROM_VALUES) {
+    if (valid) {
+      gather_nodes<NEN>(NodesPadded{coords4}, E, Xn);
+      c_e = coef[t * BLOCK + threadIdx.x];
+    }
   }
+  uint32_t em = 0;  // largest value exponent seen by this lane
+  while (true) {
+    const int64_t e = t * BLOCK + threadIdx.x;
+    for (int b = threadIdx.x; b < nb; b += BLOCK) {
+      sm.cnt[b] = 0;
+      sm.base[b] = off1[t * nb + b];
+    }
+    __syncthreads();
+    int r[NEN];
+    uint32_t q[NEN];
+    if (valid) node_ranks<NEN>(E, r);
+    const uint32_t n_items = pass1_count<NEN>(sm, E, r, valid, s1, nb, q);
+    const int64_t tn = t + nw;
+    int32_t En[NEN];
+    const bool vn = fetch(tn, En);
+    uint32_t flags = 0, fb = 0;
+    if (valid) {
+      V k[T];
+      if constexpr (FROM_VALUES)
+        read_values<T>(klow, e, k, &flags);
+      else
+        element_values_at<NEN, P>(Xn, c_e, tau, k, &flags, &fb);
+      const uint32_t me = values_emax<T>(k);
+      em = me > em ? me : em;
+      pass1_stage<NEN>(sm, E, q, k, s1);
+    }
+    if (flags) raise_flag(status, flags);
+    if (fb) atomicAdd(&status[1], fb);
+#pragma unroll
+    for (int a = 0; a < NEN; ++a) E[a] = En[a];
+    valid = vn;
+    if constexpr (!FROM_VALUES) {
+      if (valid) {
+        gather_nodes<NEN>(NodesPadded{coords4}, E, Xn);
+        c_e = coef[tn * BLOCK + threadIdx.x];
+      }
+    }
+    __syncthreads();
+    pass1_write(sm, n_items, s1, BLOCK, orow, ocol, oval);
+    t = tn;
+    if (t >= hi) break;
+    __syncthreads();
+  }
+  if (em) atomicMax(sm.emax, em);
+  __syncthreads();
+  if (threadIdx.x == 0 && *sm.emax) atomicMax(emax, *sm.emax);
 }
 
 // ------------------------------------------------------------------------ pass 2
-// Segment id -> (bucket b, index s within b); false past the last segment.
-__device__ __forceinline__ bool find_segment(int64_t sid, const uint32_t* segbase, int nb, int& b, uint32_t& s) {
-  if (sid >= (int64_t)segbase[nb]) return false;
-  int lo = 0, hi = nb - 1;  // largest b with segbase[b] <= sid
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if ((int64_t)segbase[mid] <= sid)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  b = lo;
-  s = (uint32_t)(sid - segbase[lo]);
-  return true;
+// A bucket's pairs are cut into segments of SEG; segment ids run over all buckets
+// (segbase[b] is the first segment of bucket b, segbase[nb] their number).
+
+// seg2b[s] = bucket of segment s (one workgroup per bucket)
+__global__ __launch_bounds__(256) void k_seg_map(const uint32_t* __restrict__ segbase, uint32_t* __restrict__ seg2b) {
+  const uint32_t b = blockIdx.x;
+  for (uint32_t s = segbase[b] + threadIdx.x; s < segbase[b + 1]; s += blockDim.x) seg2b[s] = b;
 }
 
-// histogram of sub-buckets per segment: hist2[segbase[b] * p2 + j * nseg_b + s], an
-// order whose exclusive scan is the position of each (segment, sub-bucket) run
+// histogram of sub-buckets ((row >> s2) mod p2) per segment: hist2[s * p2 + j]
 template <int SEG>
 __global__ __launch_bounds__(256) void k_hist2(const uint32_t* __restrict__ irow, const uint32_t* __restrict__ bstart,
-                                               const uint32_t* __restrict__ segbase, int nb, int s2, int p2,
+                                               const uint32_t* __restrict__ segbase,
+                                               const uint32_t* __restrict__ seg2b, int nb, int s2, int p2,
                                                uint32_t* __restrict__ hist2) {
   extern __shared__ uint32_t s_h[];  // [p2]
-  int b;
-  uint32_t s;
-  if (!find_segment(blockIdx.x, segbase, nb, b, s)) return;
+  const uint32_t sid = blockIdx.x;
+  if (sid >= segbase[nb]) return;
+  const uint32_t b = seg2b[sid], s = sid - segbase[b];
   for (int j = threadIdx.x; j < p2; j += blockDim.x) s_h[j] = 0;
   __syncthreads();
-  const uint32_t bs = bstart[b], be = bstart[b + 1];
-  const uint32_t i0 = bs + s * SEG, i1 = (i0 + SEG < be) ? i0 + SEG : be;
+  const uint32_t be = bstart[b + 1];
+  const uint32_t i0 = bstart[b] + s * SEG, i1 = (i0 + SEG < be) ? i0 + SEG : be;
   const uint32_t mask = (uint32_t)p2 - 1;
   for (uint32_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) atomicAdd(&s_h[(irow[i] >> s2) & mask], 1u);
   __syncthreads();
-  const uint32_t nseg = segbase[b + 1] - segbase[b];
-  const int64_t base = (int64_t)segbase[b] * p2 + s;
-  for (int j = threadIdx.x; j < p2; j += blockDim.x) hist2[base + (int64_t)j * nseg] = s_h[j];
+  for (int j = threadIdx.x; j < p2; j += blockDim.x) hist2[(int64_t)sid * p2 + j] = s_h[j];
 }
 
-// first pair of each sub-bucket: sbb[b * p2 + j]; sbb[nb * p2] = total
-__global__ void k_subbucket_starts(const uint32_t* __restrict__ off2, const uint32_t* __restrict__ bstart,
-                                   const uint32_t* __restrict__ segbase, int nb, int p2, uint32_t* __restrict__ sbb) {
-  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int64_t nsub = (int64_t)nb * p2;
-  if (g > nsub) return;
-  if (g == nsub) {
-    sbb[nsub] = bstart[nb];
-    return;
+// One workgroup per bucket b: for each sub-bucket column j, the exclusive prefix of
+// hist2 over the bucket's segments (in place), then the sub-bucket starts
+// sbb[b * p2 + j] (sbb[nb * p2] = number of pairs).  A segment's run for sub-bucket j
+// starts at sbb[b * p2 + j] + hist2[s * p2 + j].
+__global__ __launch_bounds__(256) void k_colscan(uint32_t* __restrict__ hist2, const uint32_t* __restrict__ bstart,
+                                                 const uint32_t* __restrict__ segbase, int nb, int p2,
+                                                 uint32_t* __restrict__ sbb) {
+  __shared__ uint32_t s_tot[1024];
+  __shared__ uint32_t s_scan[8];
+  const int b = blockIdx.x;
+  const uint32_t sa = segbase[b], se = segbase[b + 1];
+  for (int j = threadIdx.x; j < p2; j += blockDim.x) {
+    uint32_t run = 0;
+    uint32_t* col = hist2 + (int64_t)sa * p2 + j;
+    uint32_t s = sa;
+    for (; s + 8 <= se; s += 8, col += 8 * (int64_t)p2) {  // eight loads in flight
+      uint32_t h[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) h[q] = col[q * (int64_t)p2];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        col[q * (int64_t)p2] = run;
+        run += h[q];
+      }
+    }
+    for (; s < se; ++s, col += p2) {
+      const uint32_t h = *col;
+      *col = run;
+      run += h;
+    }
+    s_tot[j] = run;
   }
-  const int b = (int)(g / p2), j = (int)(g % p2);
-  const uint32_t nseg = segbase[b + 1] - segbase[b];
-  sbb[g] = nseg ? off2[(int64_t)segbase[b] * p2 + (int64_t)j * nseg] : bstart[b];
+  __syncthreads();
+  block_scan_array(s_tot, p2, s_scan);
+  const uint32_t bs = bstart[b];
+  for (int j = threadIdx.x; j < p2; j += blockDim.x) sbb[(int64_t)b * p2 + j] = bs + s_tot[j];
+  if (b == nb - 1 && threadIdx.x == 0) sbb[(int64_t)nb * p2] = bstart[nb];
 }
 
 // scatter a segment into its sub-buckets; output key = row_local << colbits | col
@@ -443,58 +583,53 @@ template <typename V, int SEG, int NT>
 __global__ __launch_bounds__(NT) void k_scatter2(const uint32_t* __restrict__ irow, const uint32_t* __restrict__ icol,
                                                   const V* __restrict__ ival, const uint32_t* __restrict__ bstart,
                                                   const uint32_t* __restrict__ segbase,
-                                                  const uint32_t* __restrict__ off2, int nb, int s2, int p2,
-                                                  int colbits, uint32_t* __restrict__ okey, V* __restrict__ oval) {
+                                                  const uint32_t* __restrict__ seg2b,
+                                                  const uint32_t* __restrict__ off2, const uint32_t* __restrict__ sbb,
+                                                  int nb, int s2, int p2, int colbits, uint32_t* __restrict__ okey,
+                                                  V* __restrict__ oval) {
   extern __shared__ __align__(16) unsigned char smem[];
   V* s_val = (V*)smem;                          // [SEG]
   uint32_t* s_key = (uint32_t*)(s_val + SEG);   // [SEG]
   uint16_t* s_sb = (uint16_t*)(s_key + SEG);    // [SEG] sub-bucket of staged pair
-  uint32_t* s_cnt = (uint32_t*)(s_sb + SEG);    // [p2] local starts
-  uint32_t* s_cur = s_cnt + p2;                 // [p2]
-  uint32_t* s_off = s_cur + p2;                 // [p2] global offsets
+  uint32_t* s_cnt = (uint32_t*)(s_sb + SEG);    // [p2] pairs per sub-bucket, then local starts
+  uint32_t* s_off = s_cnt + p2;                 // [p2] global offsets
   uint32_t* s_scan = s_off + p2;                // [NT/64 + 1]
-  int b;
-  uint32_t s;
-  if (!find_segment(xcd_item(blockIdx.x, gridDim.x), segbase, nb, b, s)) return;
-  const uint32_t nseg = segbase[b + 1] - segbase[b];
-  const int64_t hbase = (int64_t)segbase[b] * p2 + s;
+  const uint32_t sid = (uint32_t)xcd_item(blockIdx.x, gridDim.x);
+  if (sid >= segbase[nb]) return;
+  const uint32_t b = seg2b[sid], s = sid - segbase[b];
   for (int j = threadIdx.x; j < p2; j += blockDim.x) {
     s_cnt[j] = 0;
-    s_off[j] = off2[hbase + (int64_t)j * nseg];
+    s_off[j] = sbb[(int64_t)b * p2 + j] + off2[(int64_t)sid * p2 + j];
   }
   __syncthreads();
-  const uint32_t bs = bstart[b], be = bstart[b + 1];
-  const uint32_t i0 = bs + s * SEG, i1 = (i0 + SEG < be) ? i0 + SEG : be;
+  const uint32_t be = bstart[b + 1];
+  const uint32_t i0 = bstart[b] + s * SEG, i1 = (i0 + SEG < be) ? i0 + SEG : be;
   const uint32_t mask = (uint32_t)p2 - 1, rmask = (1u << s2) - 1;
   constexpr int PER = SEG / NT;
-  uint32_t rr[PER], cc[PER];
+  uint32_t rr[PER], cc[PER], rk[PER];
   V vv[PER];
 #pragma unroll
-  for (int q = 0; q < PER; ++q) {
+  for (int q = 0; q < PER; ++q) {  // every load issued first (indices clamped into the segment)
     const uint32_t i = i0 + q * NT + threadIdx.x;
-    if (i < i1) {
-      rr[q] = irow[i];
-      cc[q] = icol[i];
-      vv[q] = ival[i];
-    }
+    const uint32_t ic = i < i1 ? i : i0;
+    rr[q] = irow[ic];
+    cc[q] = icol[ic];
+    vv[q] = ival[ic];
   }
+  // rank of each pair within its sub-bucket, then the local run starts
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const uint32_t i = i0 + q * NT + threadIdx.x;
-    if (i < i1) atomicAdd(&s_cnt[(rr[q] >> s2) & mask], 1u);
+    if (i < i1) rk[q] = atomicAdd(&s_cnt[(rr[q] >> s2) & mask], 1u);
   }
   __syncthreads();
-  for (int j = threadIdx.x; j < p2; j += blockDim.x) s_cur[j] = s_cnt[j];
-  __syncthreads();
-  block_scan_array(s_cur, p2, s_scan);
-  for (int j = threadIdx.x; j < p2; j += blockDim.x) s_cnt[j] = s_cur[j];
-  __syncthreads();
+  block_scan_array(s_cnt, p2, s_scan);
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const uint32_t i = i0 + q * NT + threadIdx.x;
     if (i < i1) {
       const uint32_t j = (rr[q] >> s2) & mask;
-      const uint32_t pos = atomicAdd(&s_cur[j], 1u);
+      const uint32_t pos = s_cnt[j] + rk[q];
       s_key[pos] = ((rr[q] & rmask) << colbits) | cc[q];
       s_val[pos] = vv[q];
       s_sb[pos] = (uint16_t)j;
@@ -511,13 +646,12 @@ __global__ __launch_bounds__(NT) void k_scatter2(const uint32_t* __restrict__ ir
 }
 
 // ------------------------------------------------------------------------ pass 3
-__device__ __forceinline__ uint32_t key_hash(uint32_t k) {
-  k ^= k >> 16;
-  k *= 0x7FEB352Du;
-  k ^= k >> 15;
-  k *= 0x846CA68Bu;
-  k ^= k >> 16;
-  return k;
+// home slot of a packed key in a table of HT (a power of two) slots: multiplicative
+// (Fibonacci) hashing, the top bits of key * 2^32/phi
+template <int HT>
+__device__ __forceinline__ uint32_t slot_hash(uint32_t k) {
+  constexpr int bits = __builtin_ctz(HT);
+  return (k * 0x9E3779B1u) >> (32 - bits);
 }
 
 // single-lane path for a sub-bucket whose distinct entries overflow the table: heap
@@ -525,7 +659,7 @@ __device__ __forceinline__ uint32_t key_hash(uint32_t k) {
 // LDS path, which uses the same exact arithmetic).
 template <typename V>
 __device__ void pass3_global(uint32_t* key, V* val, int64_t n, int64_t r0, int R, int colbits, int F, int32_t* tcol,
-                             V* tval, int32_t* ucnt, uint32_t* usub) {
+                             V* tval, uint32_t* rowoff, uint32_t* usub) {
   auto sift = [&](int64_t root, int64_t end) {
     while (true) {
       int64_t child = 2 * root + 1;
@@ -551,7 +685,7 @@ __device__ void pass3_global(uint32_t* key, V* val, int64_t n, int64_t r0, int R
     val[end] = tv;
     sift(0, end);
   }
-  for (int r = 0; r < R; ++r) ucnt[r0 + r] = 0;
+  for (int r = 0; r < R; ++r) rowoff[r0 + r] = 0;  // counts first, offsets below
   const uint32_t cmask = (1u << colbits) - 1;
   int64_t u = 0, q = 0;
   while (q < n) {
@@ -567,21 +701,28 @@ __device__ void pass3_global(uint32_t* key, V* val, int64_t n, int64_t r0, int R
     }
     tcol[u] = (int32_t)(k0 & cmask);
     tval[u] = (V)from_fixed(lo, hi, F);
-    ucnt[r0 + (k0 >> colbits)] += 1;
+    rowoff[r0 + (k0 >> colbits)] += 1;
     ++u;
+  }
+  uint32_t run = 0;
+  for (int r = 0; r < R; ++r) {
+    const uint32_t c = rowoff[r0 + r];
+    rowoff[r0 + r] = run;
+    run += c;
   }
   *usub = (uint32_t)u;
 }
 
 // One workgroup per sub-bucket g (rows [g << s2, ...)).  Writes its unique entries in
-// CSR order to tcol/tval[sbb[g] + f], per-row unique counts to ucnt, total to usub[g].
+// CSR order to tcol/tval[sbb[g] + f], each row's first entry (relative to the
+// sub-bucket) to rowoff, its total to usub[g].
 // Sub-buckets run in their natural order: under a random numbering the lower-triangle
 // pairs of a row grow with its id, so an even interleave keeps the XCDs balanced.
 template <typename V, int HT>
 __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* __restrict__ ival,
                                                const uint32_t* __restrict__ sbb, int s2, int colbits, int64_t n_node,
                                                const uint32_t* __restrict__ emax, int32_t* __restrict__ tcol,
-                                               V* __restrict__ tval, int32_t* __restrict__ ucnt,
+                                               V* __restrict__ tval, uint32_t* __restrict__ rowoff,
                                                uint32_t* __restrict__ usub) {
   constexpr int NT = 256, PER = 4;
   __shared__ uint32_t s_key[HT];
@@ -616,7 +757,8 @@ __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* _
   }
   __syncthreads();
   // stream the pairs into the table: PER loads per lane in flight (indices clamped into
-  // the range, so every load is issued before the first use)
+  // the range; the empty asm keeps the compiler from sinking a load into the branch
+  // that first uses it)
   if (!s_over) {
     for (uint32_t i0 = beg; i0 < end; i0 += PER * NT) {
       uint32_t kk[PER];
@@ -629,28 +771,34 @@ __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* _
         vv[u] = ival[ic];
       }
 #pragma unroll
+      for (int u = 0; u < PER; ++u) asm volatile("" : "+v"(kk[u]), "+v"(vv[u]));
+#pragma unroll
       for (int u = 0; u < PER; ++u) {
         if (i0 + u * NT + threadIdx.x >= end) continue;
         const uint32_t key = kk[u];
-        uint32_t h = key_hash(key) & (HT - 1);
+        uint32_t h = slot_hash<HT>(key);
         uint32_t k = s_key[h];
-        int probes = 0;
         bool found = true;
-        while (k != key) {
-          if (k == kEmptyKey) {
-            k = atomicCAS(&s_key[h], kEmptyKey, key);
-            if (k == kEmptyKey) {  // inserted: record the slot
-              s_slot[atomicAdd(&s_nu, 1u)] = (uint16_t)h;
+        if (k != key) {  // rare: not at its home slot yet
+          int probes = 0;
+#pragma unroll 1
+          while (true) {
+            if (k == kEmptyKey) {
+              k = atomicCAS(&s_key[h], kEmptyKey, key);
+              if (k == kEmptyKey) {  // inserted: record the slot
+                s_slot[atomicAdd(&s_nu, 1u)] = (uint16_t)h;
+                break;
+              }
+              if (k == key) break;
+            }
+            if (++probes >= HT) {
+              found = false;
               break;
             }
+            h = (h + 1) & (HT - 1);
+            k = s_key[h];
             if (k == key) break;
           }
-          if (++probes >= HT) {
-            found = false;
-            break;
-          }
-          h = (h + 1) & (HT - 1);
-          k = s_key[h];
         }
         if (!found) {
           s_over = 1;
@@ -667,7 +815,7 @@ __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* _
   __syncthreads();
   if (s_over) {
     if (threadIdx.x == 0)
-      pass3_global<V>(ikey + beg, ival + beg, end - beg, r0, R, colbits, F, tcol + beg, tval + beg, ucnt, usub + g);
+      pass3_global<V>(ikey + beg, ival + beg, end - beg, r0, R, colbits, F, tcol + beg, tval + beg, rowoff, usub + g);
     return;
   }
   // order the U entries by (row, col): count per row, scan, group by row, rank by col
@@ -697,39 +845,38 @@ __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* _
     join48(s_lo[h], (int64_t)s_hi[h], lo, hi);
     tval[beg + pos] = (V)from_fixed(lo, hi, F);
   }
-  for (int r = threadIdx.x; r < R; r += NT) ucnt[r0 + r] = (int32_t)s_rc[r];
+  for (int r = threadIdx.x; r < R; r += NT) rowoff[r0 + r] = s_ro[r];
   if (threadIdx.x == 0) usub[g] = U;
 }
 
 // ------------------------------------------------------------------------- final
-// Per sub-bucket: compacted col/vals at ubase[g], row_ptr of its rows.
+// One wavefront per sub-bucket g: its entries copied to their final place ubase[g],
+// its rows' row_ptr = ubase[g] + local row offset.
 template <typename V>
 __global__ __launch_bounds__(256) void k_final(const uint32_t* __restrict__ sbb, const uint32_t* __restrict__ ubase,
                                                const int32_t* __restrict__ tcol, const V* __restrict__ tval,
-                                               const int32_t* __restrict__ ucnt, int s2, int64_t n_node, int64_t nsub,
-                                               int32_t* __restrict__ row_ptr, int32_t* __restrict__ col_idx,
-                                               V* __restrict__ vals, int64_t cap, uint32_t* __restrict__ status) {
-  __shared__ uint32_t s_r[256];
-  __shared__ uint32_t s_scan[8];
-  const int64_t g = blockIdx.x;
+                                               const uint32_t* __restrict__ rowoff, int s2, int64_t n_node,
+                                               int64_t nsub, int32_t* __restrict__ row_ptr,
+                                               int32_t* __restrict__ col_idx, V* __restrict__ vals, int64_t cap,
+                                               uint32_t* __restrict__ status) {
+  const int lane = threadIdx.x & 63;
+  const int64_t g = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (g >= nsub) return;
   const int64_t nnz = ubase[nsub];
-  const uint32_t base = ubase[g], U = ubase[g + 1] - ubase[g];
-  const int64_t r0 = g << s2, rr = n_node - r0;
-  const int R = rr <= 0 ? 0 : (rr < ((int64_t)1 << s2) ? (int)rr : (1 << s2));
+  const uint32_t base = ubase[g], U = ubase[g + 1] - base;
   if (nnz <= cap) {
     const uint32_t src = sbb[g];
-    for (uint32_t f = threadIdx.x; f < U; f += blockDim.x) {
+    for (uint32_t f = lane; f < U; f += 64) {
       col_idx[base + f] = tcol[src + f];
       vals[base + f] = tval[src + f];
     }
-  } else if (g == 0 && threadIdx.x == 0) {
+  } else if (g == 0 && lane == 0) {
     raise_flag(status, KB_F_CAPACITY);
   }
-  for (int r = threadIdx.x; r < 256; r += blockDim.x) s_r[r] = (r < R) ? (uint32_t)ucnt[r0 + r] : 0u;
-  __syncthreads();
-  block_scan_array(s_r, 256, s_scan);
-  for (int r = threadIdx.x; r < R; r += blockDim.x) row_ptr[r0 + r] = (int32_t)(base + s_r[r]);
-  if (g == nsub - 1 && threadIdx.x == 0) row_ptr[n_node] = (int32_t)nnz;
+  const int64_t r0 = g << s2;
+  const int R = (int)min((int64_t)1 << s2, n_node - r0);
+  for (int r = lane; r < R; r += 64) row_ptr[r0 + r] = (int32_t)(base + rowoff[r0 + r]);
+  if (g == nsub - 1 && lane == 0) row_ptr[n_node] = (int32_t)nnz;
 }
 
 }  // namespace kb

@@ -267,15 +267,67 @@ __device__ __forceinline__ void element_values_at(const double (&Xn)[NEN][3], do
   if (!finite) *f |= KB_F_NONFINITE;
 }
 
-// Gather and integrate element e.  E must be valid.
+// Gather and integrate element e.  E must be valid.  Each node's offset from node 0 is
+// formed as soon as it arrives, so at most two nodes' FP64 coordinates are live.
 template <int NEN, Prec P, typename NODES>
 __device__ __forceinline__ void element_values(const NODES& nodes, const double* __restrict__ coef, int64_t e,
                                                const int32_t (&E)[NEN], float tau,
                                                typename PrecTraits<P>::V (&k)[ElemTraits<NEN>::T], uint32_t* f,
                                                uint32_t* fb) {
-  double Xn[NEN][3];
-  gather_nodes<NEN>(nodes, E, Xn);
-  element_values_at<NEN, P>(Xn, coef[e], tau, k, f, fb);
+  constexpr int T = ElemTraits<NEN>::T;
+  using V = typename PrecTraits<P>::V;
+  double X0[3];
+  nodes.get(E[0], X0);
+  const double c = coef[e];
+  bool ok;
+  if constexpr (P == Prec::F64) {
+    double X[NEN][3];
+    X[0][0] = X[0][1] = X[0][2] = 0.0;
+#pragma unroll
+    for (int a = 1; a < NEN; ++a) {
+      double xa[3];
+      nodes.get(E[a], xa);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) X[a][j] = xa[j] - X0[j];
+    }
+    ok = integrate<NEN, double, double, false>(X, k, 0.0, nullptr);
+  } else {
+    float X[NEN][3];
+    X[0][0] = X[0][1] = X[0][2] = 0.f;
+#pragma unroll
+    for (int a = 1; a < NEN; ++a) {
+      double xa[3];
+      nodes.get(E[a], xa);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) X[a][j] = (float)(xa[j] - X0[j]);
+    }
+    bool need_fb = false;
+    ok = integrate<NEN, float, float, P == Prec::F32FB>(X, k, tau, &need_fb);
+    if constexpr (P == Prec::F32FB) {
+      if (need_fb) {
+        // Jacobian, determinant and adjugate in FP64 for this element (nodes re-read)
+        double Xd[NEN][3];
+        Xd[0][0] = Xd[0][1] = Xd[0][2] = 0.0;
+#pragma unroll
+        for (int a = 1; a < NEN; ++a) {
+          double xa[3];
+          nodes.get(E[a], xa);
+#pragma unroll
+          for (int j = 0; j < 3; ++j) Xd[a][j] = xa[j] - X0[j];
+        }
+        ok = integrate<NEN, double, float, false>(Xd, k, 0.0, nullptr);
+        *fb += 1;
+      }
+    }
+  }
+  bool finite = true;
+#pragma unroll
+  for (int p = 0; p < T; ++p) {
+    k[p] = (V)(c * (double)k[p]);
+    finite = finite && isfinite((double)k[p]);
+  }
+  if (!ok) *f |= KB_F_INVERTED;
+  if (!finite) *f |= KB_F_NONFINITE;
 }
 
 template <int NEN, Prec P>
