@@ -90,7 +90,7 @@ def stored_traffic(kernel: str, workload: str, prec: str):
         if ":" in line and line.strip().startswith(("traffic_bytes", "source_sha256")):
             k, v = line.strip().split(":", 1)
             fields[k.strip()] = v.strip().strip("`")
-    sec = [l for l in open(path).read().split("\n## ") if l.startswith(kernel)]
+    sec = [l for l in open(path).read().split("\n## ") if l.split("\n", 1)[0].strip() == kernel]
     if not sec or fields.get("source_sha256") != source_digest():
         return None
     for line in sec[0].splitlines():
