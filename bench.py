@@ -37,7 +37,8 @@ def algorithmic_bytes(elem: int, n_elem: int, n_node: int, nnz: int, prec: str) 
     """Compulsory HBM bytes of each stage and of the whole path (per launch).
 
     Per stage: its inputs read once and its outputs written once, in the formats the
-    stages exchange: (row, col, value) after pass 1, (packed key, value) after pass 2.
+    stages exchange: (16-bit row within its bucket, col, value) after pass 1, (packed key,
+    value) after pass 2.
     For the path: E, c and C read once (coordinates once per node), the lower values
     written once and read once, CSR written once.
     """
@@ -50,9 +51,9 @@ def algorithmic_bytes(elem: int, n_elem: int, n_node: int, nnz: int, prec: str) 
     coords = 24 * n_node
     b = {
         "count": conn,                                            # E in (histogram out is small)
-        "integrate": conn + coef + coords + (8 + vb) * T,         # E, c, C in; (row, col, value) out
-        "histogram": 4 * T,                                       # rows in (histograms out are small)
-        "partition": (8 + vb) * T + (4 + vb) * T,                 # (row, col, value) in, (key, value) out
+        "integrate": conn + coef + coords + (6 + vb) * T,         # E, c, C in; (row16, col, value) out
+        "histogram": 2 * T,                                       # rows in (histograms out are small)
+        "partition": (6 + vb) * T + (4 + vb) * T,                 # (row16, col, value) in, (key, value) out
         "reduce": (4 + vb) * T + (4 + vb) * nnz + 4 * n_node,     # pairs in; unique entries, row counts out
         "compress": 2 * (4 + vb) * nnz + 8 * n_node,              # unique entries in, CSR out
     }

@@ -114,7 +114,7 @@ typedef struct {
                               it equals the default element tile of the build or half
                               of it (tet4: 1024 / 512, FP64 768 / 384; hex8: 256 / 128,
                               FP64 192 / 128) it also sets that tile                    */
-  int32_t bucket_bits;     /* log2 rows per first-level bucket (0 = from mesh shape)    */
+  int32_t bucket_bits;     /* log2 rows per first-level bucket, <= 16 (0 = from mesh shape) */
   float fb_tau;            /* KB_FP32_FB64 condition-number threshold (> 1)             */
   int32_t sub_bits;        /* log2 rows per sub-bucket, <= bucket_bits and <= 8 (0 = auto) */
   void** stage_events;     /* NULL, or KB_N_STAGES + 1 hipEvent_t: event i is recorded

@@ -97,7 +97,7 @@ int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p) {
       if (!(tu->fb_tau > 1.0f)) return KB_EINVAL;
       p->tau = tu->fb_tau;
     }
-    if (tu->sub_bits < 0 || tu->sub_bits > 8 || tu->bucket_bits < 0 || tu->bucket_bits > 30) return KB_EINVAL;
+    if (tu->sub_bits < 0 || tu->sub_bits > 8 || tu->bucket_bits < 0 || tu->bucket_bits > 16) return KB_EINVAL;
     if (tu->bucket_bits && tu->sub_bits && tu->sub_bits > tu->bucket_bits) return KB_EINVAL;
     bucket_bits = tu->bucket_bits;
     sub_bits = tu->sub_bits;
@@ -127,7 +127,8 @@ int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p) {
     const int64_t nsub_min = div_up(p->nn > 0 ? p->nn : 1, (int64_t)1 << p->s2);
     int d = ilog2_ceil(div_up(nsub_min, kTargetBuckets));
     if (d > 10) d = 10;
-    p->s1 = p->s2 + d;
+    // rows are stored within their bucket in 16 bits: at most 2^16 rows per bucket
+    p->s1 = std::min(16, p->s2 + d);
   }
   if (p->s1 - p->s2 > 10) return KB_EINVAL;
   p->p2 = 1 << (p->s1 - p->s2);
@@ -166,7 +167,7 @@ int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p) {
   p->o_hist2 = take(4 * (size_t)(p->nseg_max * p->p2));
   p->o_seg2b = take(4 * (size_t)p->nseg_max);
   p->o_emax = take(4);
-  p->o_row1 = take(4 * T);
+  p->o_row1 = take(2 * T);
   p->o_col1 = take(4 * T);
   p->o_val1 = take(p->vbytes * T);
   p->o_key2 = take(4 * T);
@@ -251,7 +252,7 @@ int launch_pass1_block(const Plan& p, const kb_mesh* m, const void* klow, unsign
                : std::min<int64_t>(p.ntiles, std::max<int64_t>(8, (int64_t)p.cus * std::min(per_cu, 2048 / BLOCK)));
   kern<<<(unsigned)g1, BLOCK, p.lds1, s>>>(m->conn, (const double4*)(ws + p.o_coords4), m->coef, (const V*)klow, p.nel,
                                            p.nn, p.tau, p.s1, p.nb, p.ntiles, (const uint32_t*)(ws + p.o_hist),
-                                           (uint32_t*)(ws + p.o_row1), (uint32_t*)(ws + p.o_col1),
+                                           (uint16_t*)(ws + p.o_row1), (uint32_t*)(ws + p.o_col1),
                                            (V*)(ws + p.o_val1), (uint32_t*)(ws + p.o_emax), status);
   KB_LAUNCH_CHECK();
   return KB_OK;
@@ -283,7 +284,7 @@ int assemble_tail(const Plan& p, unsigned char* ws, int32_t* row_ptr, int32_t* c
   auto* hist2 = (uint32_t*)(ws + p.o_hist2);
   auto* seg2b = (uint32_t*)(ws + p.o_seg2b);
   auto* emax = (uint32_t*)(ws + p.o_emax);
-  auto* row1 = (uint32_t*)(ws + p.o_row1);
+  auto* row1 = (uint16_t*)(ws + p.o_row1);
   auto* col1 = (uint32_t*)(ws + p.o_col1);
   auto* val1 = (V*)(ws + p.o_val1);
   auto* key2 = (uint32_t*)(ws + p.o_key2);
@@ -294,7 +295,7 @@ int assemble_tail(const Plan& p, unsigned char* ws, int32_t* row_ptr, int32_t* c
   auto* ubase = (uint32_t*)(ws + p.o_ubase);
   auto* part = (int32_t*)(ws + p.o_part);
   // pass-3 output reuses the pass-1 buffers (dead after pass 2)
-  auto* tcol = (int32_t*)row1;
+  auto* tcol = (int32_t*)col1;
   auto* tval = val1;
   KB_TRY(ev.rec(KB_STAGE_HISTOGRAM));
   if (p.nb > 0) {

@@ -331,14 +331,14 @@ __device__ __forceinline__ void pass1_stage(const SM& sm, const int32_t (&E)[NEN
 // write the staged pairs: index i lies in bucket b = row >> s1, local start sm.cnt[b]
 template <typename V, typename SM>
 __device__ __forceinline__ void pass1_write(const SM& sm, uint32_t n_items, int s1, int nthreads,
-                                            uint32_t* __restrict__ orow, uint32_t* __restrict__ ocol,
+                                            uint16_t* __restrict__ orow, uint32_t* __restrict__ ocol,
                                             V* __restrict__ oval) {
   for (uint32_t i = threadIdx.x; i < n_items; i += nthreads) {
     const uint64_t key = sm.key[i];
     const uint32_t row = (uint32_t)(key >> 32);
     const int b = (int)(row >> s1);
     const uint32_t g = sm.base[b] + (i - sm.cnt[b]);
-    orow[g] = row;
+    orow[g] = (uint16_t)(row & ((1u << s1) - 1));  // row within its bucket
     ocol[g] = (uint32_t)key;
     oval[g] = sm.val[i];
   }
@@ -375,7 +375,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass1(const int32_t* __restrict__ con
                                                const double* __restrict__ coef,
                                                const typename PrecTraits<P>::V* __restrict__ klow, int64_t n_elem,
                                                int64_t n_node, float tau, int s1, int nb, int64_t ntiles,
-                                               const uint32_t* __restrict__ off1, uint32_t* __restrict__ orow,
+                                               const uint32_t* __restrict__ off1, uint16_t* __restrict__ orow,
                                                uint32_t* __restrict__ ocol, typename PrecTraits<P>::V* __restrict__ oval,
                                                uint32_t* __restrict__ emax, uint32_t* __restrict__ status) {
   using V = typename PrecTraits<P>::V;
@@ -427,7 +427,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass1_tet(const int32_t* __restrict__
                                                    const double* __restrict__ coef,
                                                    const typename PrecTraits<P>::V* __restrict__ klow, int64_t n_elem,
                                                    int64_t n_node, float tau, int s1, int nb, int64_t ntiles,
-                                                   const uint32_t* __restrict__ off1, uint32_t* __restrict__ orow,
+                                                   const uint32_t* __restrict__ off1, uint16_t* __restrict__ orow,
                                                    uint32_t* __restrict__ ocol,
                                                    typename PrecTraits<P>::V* __restrict__ oval,
                                                    uint32_t* __restrict__ emax, uint32_t* __restrict__ status) {
@@ -521,7 +521,7 @@ __global__ __launch_bounds__(256) void k_seg_map(const uint32_t* __restrict__ se
 
 // histogram of sub-buckets ((row >> s2) mod p2) per segment: hist2[s * p2 + j]
 template <int SEG>
-__global__ __launch_bounds__(256) void k_hist2(const uint32_t* __restrict__ irow, const uint32_t* __restrict__ bstart,
+__global__ __launch_bounds__(256) void k_hist2(const uint16_t* __restrict__ irow, const uint32_t* __restrict__ bstart,
                                                const uint32_t* __restrict__ segbase,
                                                const uint32_t* __restrict__ seg2b, int nb, int s2, int p2,
                                                uint32_t* __restrict__ hist2) {
@@ -580,7 +580,7 @@ __global__ __launch_bounds__(256) void k_colscan(uint32_t* __restrict__ hist2, c
 
 // scatter a segment into its sub-buckets; output key = row_local << colbits | col
 template <typename V, int SEG, int NT>
-__global__ __launch_bounds__(NT) void k_scatter2(const uint32_t* __restrict__ irow, const uint32_t* __restrict__ icol,
+__global__ __launch_bounds__(NT) void k_scatter2(const uint16_t* __restrict__ irow, const uint32_t* __restrict__ icol,
                                                   const V* __restrict__ ival, const uint32_t* __restrict__ bstart,
                                                   const uint32_t* __restrict__ segbase,
                                                   const uint32_t* __restrict__ seg2b,
@@ -730,7 +730,7 @@ __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* _
   __shared__ unsigned long long s_hi[HT];  // sum of signed high chunks
   __shared__ uint16_t s_slot[HT];  // occupied slots, in insertion order
   __shared__ uint16_t s_w[HT];     // index of each occupied slot within its row
-  __shared__ uint16_t s_list[HT];  // occupied slots grouped by row
+  __shared__ uint32_t s_lcol[HT];  // columns of the occupied slots, grouped by row
   __shared__ uint32_t s_rc[256];   // entries per row
   __shared__ uint32_t s_ro[256];   // row offsets
   __shared__ uint32_t s_scan[8];
@@ -829,7 +829,7 @@ __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* _
   block_scan_array(s_ro, RB, s_scan);
   for (uint32_t f = threadIdx.x; f < U; f += NT) {
     const uint32_t h = s_slot[f];
-    s_list[s_ro[s_key[h] >> colbits] + s_w[f]] = (uint16_t)h;
+    s_lcol[s_ro[s_key[h] >> colbits] + s_w[f]] = s_key[h] & cmask;
   }
   __syncthreads();
   for (uint32_t f = threadIdx.x; f < U; f += NT) {
@@ -838,7 +838,7 @@ __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* _
     const uint32_t row = k >> colbits, col = k & cmask;
     const uint32_t ro = s_ro[row], nr = s_rc[row];
     uint32_t rank = 0;
-    for (uint32_t q = 0; q < nr; ++q) rank += ((s_key[s_list[ro + q]] & cmask) < col) ? 1u : 0u;
+    for (uint32_t q = 0; q < nr; ++q) rank += (s_lcol[ro + q] < col) ? 1u : 0u;
     const uint32_t pos = ro + rank;
     tcol[beg + pos] = (int32_t)col;
     uint64_t lo, hi;

@@ -67,8 +67,9 @@ def test_plan_sizes(elem, te, prec):
     rc, ws, nt = _plan(elem, 1000, 1331, prec)
     assert rc == 0 and nt == 1000 * te
     vb = 8 if prec == 0 else 4
-    # at least: (row, col, value) and (packed key, value) pair lists, per-node unique counts
-    assert ws >= nt * (12 + 2 * vb) + 4 * 1331
+    # at least: (16-bit row in bucket, col, value) and (packed key, value) pair lists,
+    # per-node row offsets
+    assert ws >= nt * (10 + 2 * vb) + 4 * 1331
     assert ws % 256 == 0
 
 
@@ -89,6 +90,7 @@ def test_plan_errors():
     assert _plan(4, 2**31 // 10, 10)[0] == 0
     assert _plan(8, 10, 10, tuning=KbTuning(100, 0, 0.0, 0, None))[0] == _lib.KB_EINVAL  # block not multiple of 64
     assert _plan(8, 10, 10, tuning=KbTuning(0, 31, 0.0, 0, None))[0] == _lib.KB_EINVAL  # bucket bits
+    assert _plan(8, 10, 10, tuning=KbTuning(0, 17, 0.0, 8, None))[0] == _lib.KB_EINVAL  # rows in bucket > 2^16
     assert _plan(8, 10, 10, tuning=KbTuning(0, 0, 0.5, 0, None))[0] == _lib.KB_EINVAL  # tau <= 1
     assert _plan(8, 10, 10, tuning=KbTuning(0, 0, 0.0, 9, None))[0] == _lib.KB_EINVAL  # sub-bucket bits > 8
     assert _plan(8, 10, 10, tuning=KbTuning(0, 3, 0.0, 5, None))[0] == _lib.KB_EINVAL  # sub > bucket
