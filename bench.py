@@ -30,6 +30,8 @@ WORKLOADS = {
     "c3": (3, "tet4 Kuhn 6x150^3 (20,250,000 elements, 3,442,951 nodes), jitter 0.2h, random node and element "
               "numbering, c log-U[1e-3,1e3], 1-point rule", "fp32fb64"),
     "c5": (5, "hex8 box 64^3 (262,144 elements), jitter 0.2h, c log-U[1e-1,1e1]", "fp64"),
+    "c4": (4, "256 hex8 boxes, cells per axis U{8..64}, h=1/64, jitter 0.2h, c log-U[1e-2,1e2], one batched "
+              "build", "fp32fb64"),
 }
 
 
@@ -120,12 +122,19 @@ def parse():
 
 
 def time_builds(kb, torch, mesh_dev, m, prec, steps, warmup, stage_events=True, tuning=None):
-    conn, coords, coef = mesh_dev
-    b = kb.Builder(m.elem, m.n_elem, m.n_node, prec=prec, tuning=tuning)
+    if isinstance(mesh_dev, kb.Batch):
+        b = kb.BatchBuilder(mesh_dev, prec=prec, tuning=tuning)
+        run = lambda ev=None: b.run(stage_events=ev)  # noqa: E731
+        result = lambda: b.results(check=True)  # noqa: E731
+    else:
+        conn, coords, coef = mesh_dev
+        b = kb.Builder(m.elem, m.n_elem, m.n_node, prec=prec, tuning=tuning)
+        run = lambda ev=None: b.run(conn, coords, coef, stage_events=ev)  # noqa: E731
+        result = lambda: b.result(check=True, allow_flags=0)  # noqa: E731
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
-        b.run(conn, coords, coef)
-    res = b.result(check=True, allow_flags=0)
+        run()
+    res = result()
     n_ev = kb.KB_N_STAGES + 1
     evs = [kb._lib.HipEvents(n_ev) for _ in range(steps)] if stage_events else None
     torch.cuda.synchronize()
@@ -134,7 +143,7 @@ def time_builds(kb, torch, mesh_dev, m, prec, steps, warmup, stage_events=True, 
     wall0 = time.perf_counter()
     t0.record(stream)
     for s in range(steps):
-        b.run(conn, coords, coef, stage_events=evs[s].handles if evs else None)
+        run(evs[s].handles if evs else None)
     t1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
@@ -146,8 +155,15 @@ def time_builds(kb, torch, mesh_dev, m, prec, steps, warmup, stage_events=True, 
             stages[name] = sum(evs[s].elapsed_ms(i, i + 1) for s in range(steps)) / steps
         for e in evs:
             e.close()
-    res = b.result(check=True, allow_flags=0)
+    res = result()
+    if isinstance(res, list):  # a batch: totals over its meshes
+        res = BatchTotals(sum(r.nnz for r in res), res[0].n_fallback if res else 0)
     return ms, wall / steps * 1e3, stages, res
+
+
+class BatchTotals:
+    def __init__(self, nnz, n_fallback):
+        self.nnz, self.n_fallback = nnz, n_fallback
 
 
 def cpu_baseline(m, sample):
@@ -156,6 +172,17 @@ def cpu_baseline(m, sample):
     import meshgen
     import oracle
 
+    if isinstance(m, list):  # a batch: whole meshes in order until the sample is reached
+        oracle.lib()
+        done, k, t = 0, 0, time.perf_counter()
+        while k < len(m) and done < sample:
+            oracle.build_mesh(m[k])
+            done += m[k].n_elem
+            k += 1
+        dt = time.perf_counter() - t
+        return {"value": done / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
+                "sample": f"the first {k} of {len(m)} meshes ({done:,} elements), each built separately by the "
+                          f"single-threaded FP64 C oracle, {dt:.1f} s"}
     n = min(sample, m.n_elem)
     sub = meshgen.Mesh(m.elem, np.ascontiguousarray(m.conn[:n]), m.coords, np.ascontiguousarray(m.coef[:n]))
     oracle.lib()
@@ -165,6 +192,11 @@ def cpu_baseline(m, sample):
     return {"value": n / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
             "sample": f"first {n:,} of the {m.n_elem:,} elements (all {m.n_node:,} nodes), single-threaded FP64 "
                       f"C oracle, integrate + sort + CSR, {dt:.1f} s"}
+
+
+class MeshTotals:
+    def __init__(self, elem, n_elem, n_node):
+        self.elem, self.n_elem, self.n_node = elem, n_elem, n_node
 
 
 def main():
@@ -189,9 +221,15 @@ def main():
     cid, desc, default_prec = WORKLOADS[args.workload]
     prec = args.prec or default_prec
     print(f"[bench] generating workload {args.workload}: {desc}", file=sys.stderr, flush=True)
-    m = meshgen.config_mesh(cid)
     dev = torch.device("cuda:0")
-    mesh_dev = (torch.from_numpy(m.conn).to(dev), torch.from_numpy(m.coords).to(dev), torch.from_numpy(m.coef).to(dev))
+    if cid == 4:
+        meshes = meshgen.config4_batch()
+        mesh_dev = kb.pack_batch([(x.conn, x.coords, x.coef) for x in meshes], 8, dev)
+        m = MeshTotals(8, sum(x.n_elem for x in meshes), sum(x.n_node for x in meshes))
+    else:
+        m = meshgen.config_mesh(cid)
+        mesh_dev = (torch.from_numpy(m.conn).to(dev), torch.from_numpy(m.coords).to(dev),
+                    torch.from_numpy(m.coef).to(dev))
     torch.cuda.synchronize()
     print(f"[bench] {m.n_elem} elements, {m.n_node} nodes on device; timing {prec}", file=sys.stderr, flush=True)
 
@@ -230,7 +268,7 @@ def main():
         print(f"[bench] fp64: {ms64:.3f} ms/step", file=sys.stderr, flush=True)
     if not args.no_cpu:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(m, args.cpu_sample)
+        out["cpu_baseline"] = cpu_baseline(meshes if cid == 4 else m, args.cpu_sample)
     print(json.dumps(out), flush=True)
 
 

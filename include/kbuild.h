@@ -27,7 +27,7 @@
  * Precision modes (value type of vals / per-element outputs in parentheses):
  *   KB_FP64       all arithmetic in FP64 (double);
  *   KB_FP32       node coordinates are differenced in FP64 against the element's first
- *                 node, the rest of the integration runs in FP32; assembly sums in FP64
+ *                 node, the rest of the integration runs in FP32; assembly sums exactly
  *                 and rounds each entry once (float);
  *   KB_FP32_FB64  as KB_FP32, but an element whose Jacobian at some integration point
  *                 has an estimated infinity-norm condition number above tau gets its
@@ -162,6 +162,49 @@ int kb_integrate_lower(const kb_mesh* mesh, int prec, const kb_tuning* tuning, v
 int kb_assemble_lower_csr(const kb_mesh* mesh, int prec, const kb_tuning* tuning, const void* klow, void* ws,
                           size_t ws_bytes, int32_t* row_ptr, int32_t* col_idx, void* vals, int64_t cap,
                           int64_t* nnz_dev, uint32_t* status_dev, void* stream);
+
+/*
+ * Batches.  Many independent meshes of one element type, built by one enqueued sequence
+ * of kernels (no host synchronisation, so the whole call can be captured in a HIP graph).
+ * The meshes are packed back to back: mesh m owns elements [elem_off[m], elem_off[m+1])
+ * and nodes [node_off[m], node_off[m+1]); its connectivity holds node ids local to the
+ * mesh (0 .. node_off[m+1] - node_off[m] - 1).  No element couples two meshes, so the
+ * batch's K is block diagonal and each mesh's lower CSR is what kb_build_lower_csr
+ * gives for that mesh alone.  (Section 3, Eq. 10 splits one large mesh into element
+ * groups integrated one after another; a batch is the converse case, many meshes too
+ * small to fill the device, and is built in a single pass.)
+ */
+typedef struct {
+  int32_t elem;             /* KB_HEX8 or KB_TET4, for every mesh                          */
+  int32_t n_mesh;           /* number of meshes (>= 0)                                    */
+  int64_t n_elem;           /* total elements                                             */
+  int64_t n_node;           /* total nodes                                                */
+  const int64_t* elem_off;  /* device [n_mesh + 1]: 0, ..., n_elem (non-decreasing)          */
+  const int64_t* node_off;  /* device [n_mesh + 1]: 0, ..., n_node (non-decreasing)          */
+  const int32_t* conn;      /* device [n_elem][nen], node ids local to each mesh           */
+  const double* coords;     /* device [n_node][3]                                          */
+  const double* coef;       /* device [n_elem]                                             */
+} kb_batch;
+
+/* Workspace and triplet bound for a batch (host only; reads elem, n_mesh, n_elem,
+ * n_node).  Returns as kb_plan; T and n_node are the batch totals. */
+int kb_plan_batched(const kb_batch* batch, int prec, const kb_tuning* tuning, size_t* ws_bytes,
+                    int64_t* n_triplets);
+
+/*
+ * Build every mesh of a batch.  Outputs (device):
+ *   row_ptr  [n_node + n_mesh]: mesh m's row pointers (node_off[m+1] - node_off[m] + 1
+ *            entries, the first 0) start at row_ptr[node_off[m] + m];
+ *   col_idx, vals [cap]: mesh m's entries, mesh-local column ids, start at nnz_off[m];
+ *   nnz_off  int64 [n_mesh + 1]: nnz_off[n_mesh] = total nnz;
+ *   status_dev as for kb_build_lower_csr; offsets that do not start at 0, decrease or
+ *            do not end at the totals, and local ids outside their mesh, set KB_F_INDEX.
+ * If the total nnz exceeds cap, KB_F_CAPACITY is set and col_idx / vals are not
+ * written (row_ptr and nnz_off still are).  Workspace from kb_plan_batched.
+ */
+int kb_build_lower_csr_batched(const kb_batch* batch, int prec, const kb_tuning* tuning, void* ws, size_t ws_bytes,
+                               int32_t* row_ptr, int32_t* col_idx, void* vals, int64_t cap, int64_t* nnz_off,
+                               uint32_t* status_dev, void* stream);
 
 /* Static text for a return code (negative) or a single status flag bit (positive). */
 const char* kb_status_string(int code);

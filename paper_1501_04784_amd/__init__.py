@@ -18,7 +18,7 @@ import torch
 
 from . import _lib
 from ._lib import (KB_F_CAPACITY, KB_F_INDEX, KB_F_INVERTED, KB_F_NONFINITE, KB_F_REPEAT, KB_FP32, KB_FP32_FB64,
-                   KB_FP64, KB_HEX8, KB_N_STAGES, KB_STATUS_WORDS, KB_TET4, STAGE_NAMES, KbMesh, KbTuning)
+                   KB_FP64, KB_HEX8, KB_N_STAGES, KB_STATUS_WORDS, KB_TET4, STAGE_NAMES, KbBatch, KbMesh, KbTuning)
 
 PRECISIONS = {"fp64": KB_FP64, "fp32": KB_FP32, "fp32fb64": KB_FP32_FB64}
 FLAG_NAMES = {KB_F_INDEX: "index", KB_F_REPEAT: "repeat", KB_F_INVERTED: "inverted", KB_F_NONFINITE: "nonfinite",
@@ -63,7 +63,7 @@ def _mesh(elem, n_elem, n_node, conn=None, coords=None, coef=None) -> KbMesh:
                   None if coords is None else coords.data_ptr(), None if coef is None else coef.data_ptr())
 
 
-@dataclass
+@dataclass(frozen=True)
 class Tuning:
     block: int = 0
     bucket_bits: int = 0
@@ -228,6 +228,161 @@ def integrate_lower(conn, coords, coef, elem: int, prec="fp64", tuning: Tuning |
     return out, status
 
 
-__all__ = ["Builder", "LowerCSR", "KBuildError", "Tuning", "build_lower_csr", "assemble_lower_csr",
-           "integrate_lower", "plan", "status_string", "version", "value_dtype", "STAGE_NAMES", "KB_N_STAGES",
+# ---- batches -------------------------------------------------------------------------
+@dataclass
+class Batch:
+    """Meshes packed back to back (device tensors): connectivity in mesh-local ids."""
+
+    elem: int
+    conn: torch.Tensor      # int32 [n_elem, nen]
+    coords: torch.Tensor    # float64 [n_node, 3]
+    coef: torch.Tensor      # float64 [n_elem]
+    elem_off: torch.Tensor  # int64 [n_mesh + 1]
+    node_off: torch.Tensor  # int64 [n_mesh + 1]
+    elem_off_host: tuple = ()
+    node_off_host: tuple = ()
+
+    @property
+    def n_mesh(self) -> int:
+        return int(self.elem_off.numel()) - 1
+
+    def to_c(self) -> KbBatch:
+        return KbBatch(int(self.elem), self.n_mesh, int(self.conn.shape[0]), int(self.coords.shape[0]),
+                       self.elem_off.data_ptr(), self.node_off.data_ptr(), self.conn.data_ptr(),
+                       self.coords.data_ptr(), self.coef.data_ptr())
+
+
+def pack_batch(meshes, elem: int, device="cuda") -> Batch:
+    """Pack [(conn, coords, coef), ...] (array-likes, mesh-local ids) into one Batch."""
+    import numpy as np
+
+    conns, xs, cs, eo, no = [], [], [], [0], [0]
+    for conn, coords, coef in meshes:
+        conns.append(np.asarray(conn, dtype=np.int32).reshape(-1, elem))
+        xs.append(np.asarray(coords, dtype=np.float64).reshape(-1, 3))
+        cs.append(np.asarray(coef, dtype=np.float64).reshape(-1))
+        eo.append(eo[-1] + conns[-1].shape[0])
+        no.append(no[-1] + xs[-1].shape[0])
+    dev = torch.device(device)
+    cat = (lambda a, shape, dt: torch.from_numpy(np.concatenate(a) if a else np.zeros(shape, dtype=dt)).to(dev))
+    return Batch(elem, cat(conns, (0, elem), np.int32), cat(xs, (0, 3), np.float64), cat(cs, (0,), np.float64),
+                 torch.tensor(eo, dtype=torch.int64, device=dev), torch.tensor(no, dtype=torch.int64, device=dev),
+                 tuple(eo), tuple(no))
+
+
+def plan_batched(elem: int, n_mesh: int, n_elem: int, n_node: int, prec="fp32fb64", tuning: Tuning | None = None):
+    ws = ctypes.c_size_t(0)
+    nt = ctypes.c_int64(0)
+    b = KbBatch(int(elem), int(n_mesh), int(n_elem), int(n_node), None, None, None, None, None)
+    tu = (tuning or Tuning()).to_c()
+    _check(_lib.lib().kb_plan_batched(ctypes.byref(b), _prec(prec), ctypes.byref(tu), ctypes.byref(ws),
+                                      ctypes.byref(nt)), "kb_plan_batched")
+    return int(ws.value), int(nt.value)
+
+
+class BatchBuilder:
+    """Reusable batched build: workspace and outputs allocated once for a batch shape.
+
+    ``run`` enqueues the whole batch on the current stream and allocates nothing, so it
+    can be captured in a HIP graph (``torch.cuda.graph``) and replayed.
+    """
+
+    def __init__(self, batch: Batch, prec="fp32fb64", tuning: Tuning | None = None, cap: int | None = None):
+        self.batch = batch
+        self.prec = _prec(prec)
+        self.tuning = tuning or Tuning()
+        n_elem, n_node = int(batch.conn.shape[0]), int(batch.coords.shape[0])
+        self.ws_bytes, self.n_triplets = plan_batched(batch.elem, batch.n_mesh, n_elem, n_node, self.prec, self.tuning)
+        self.cap = self.n_triplets if cap is None else int(cap)
+        dev = batch.conn.device
+        self.ws = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=dev)
+        self.row_ptr = torch.empty(n_node + batch.n_mesh, dtype=torch.int32, device=dev)
+        self.col_idx = torch.empty(max(self.cap, 1), dtype=torch.int32, device=dev)
+        self.vals = torch.empty(max(self.cap, 1), dtype=value_dtype(self.prec), device=dev)
+        self.nnz_off = torch.zeros(batch.n_mesh + 1, dtype=torch.int64, device=dev)
+        self.status = torch.zeros(KB_STATUS_WORDS, dtype=torch.int32, device=dev)
+        self._c = batch.to_c()
+
+    def run(self, stream=None, stage_events=None):
+        s = stream if stream is not None else torch.cuda.current_stream()
+        ev = None
+        if stage_events is not None:
+            arr = (ctypes.c_void_p * len(stage_events))(*[int(e) for e in stage_events])
+            self._ev_keep = arr
+            ev = ctypes.cast(arr, ctypes.c_void_p)
+        tu = self.tuning.to_c(ev)
+        rc = _lib.lib().kb_build_lower_csr_batched(ctypes.byref(self._c), self.prec, ctypes.byref(tu), _ptr(self.ws),
+                                                   self.ws_bytes, _ptr(self.row_ptr), _ptr(self.col_idx),
+                                                   _ptr(self.vals), self.cap, _ptr(self.nnz_off), _ptr(self.status),
+                                                   ctypes.c_void_p(s.cuda_stream))
+        _check(rc, "kb_build_lower_csr_batched")
+
+    def results(self, check: bool = True, allow_flags: int = 0) -> list:
+        """Synchronise; one LowerCSR (views into the batch outputs) per mesh."""
+        torch.cuda.current_stream().synchronize()
+        flags = int(self.status[0].item()) & 0xFFFFFFFF
+        if check:
+            _raise_on_flags(flags, allow_flags)
+        off = self.nnz_off.cpu().tolist()
+        no = self.batch.node_off_host or tuple(self.batch.node_off.cpu().tolist())
+        st = self.status.clone()
+        out = []
+        for m in range(self.batch.n_mesh):
+            rp = self.row_ptr[no[m] + m: no[m + 1] + m + 1]
+            ok = off[-1] <= self.cap
+            out.append(LowerCSR(rp, self.col_idx[off[m]:off[m + 1]] if ok else self.col_idx[:0],
+                                self.vals[off[m]:off[m + 1]] if ok else self.vals[:0], off[m + 1] - off[m], st))
+        return out
+
+
+def build_lower_csr_batched(meshes, elem: int, prec="fp32fb64", tuning: Tuning | None = None, check=True,
+                            allow_flags: int = 0, device="cuda") -> list:
+    """Build each mesh of [(conn, coords, coef), ...] (mesh-local ids) in one batched call."""
+    b = BatchBuilder(pack_batch(meshes, elem, device), prec, tuning)
+    b.run()
+    return b.results(check=check, allow_flags=allow_flags)
+
+
+# ---- tuning search ---------------------------------------------------------------------
+def autotune(run_with, candidates, reps: int = 3, warmup: int = 1):
+    """Time ``run_with(tuning)`` (enqueues one build) for each candidate Tuning with HIP
+    events on the current stream; return (best tuning, {candidate: ms})."""
+    timings = {}
+    stream = torch.cuda.current_stream()
+    for t in candidates:
+        try:
+            for _ in range(warmup):
+                run_with(t)
+        except KBuildError:
+            continue  # not a valid configuration for this shape
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            run_with(t)
+        e1.record(stream)
+        e1.synchronize()
+        timings[t] = e0.elapsed_time(e1) / reps
+    if not timings:
+        raise KBuildError("no candidate tuning is valid for this shape")
+    best = min(timings, key=timings.get)
+    return best, timings
+
+
+def default_candidates(elem: int, prec="fp32fb64"):
+    """Tile size, first-level bucket width and sub-bucket width around the defaults."""
+    big = {(4, KB_FP64): 768, (8, KB_FP64): 192}.get((elem, _prec(prec)), 1024 if elem == 4 else 256)
+    small = big // 2 if (big // 2) % 64 == 0 else 64 * ((big // 2 + 63) // 64)
+    out = [Tuning()]
+    for blk in (big, small):
+        for bb in (0, 12, 14):
+            for sb in (0, 4, 5):
+                t = Tuning(block=blk, bucket_bits=bb, sub_bits=sb)
+                if t not in out:
+                    out.append(t)
+    return out
+
+
+__all__ = ["Builder", "BatchBuilder", "Batch", "LowerCSR", "KBuildError", "Tuning", "build_lower_csr",
+           "build_lower_csr_batched", "assemble_lower_csr", "integrate_lower", "pack_batch", "plan", "plan_batched",
+           "autotune", "default_candidates", "status_string", "version", "value_dtype", "STAGE_NAMES", "KB_N_STAGES",
            "KB_HEX8", "KB_TET4", "KB_FP64", "KB_FP32", "KB_FP32_FB64"]

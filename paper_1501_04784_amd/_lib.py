@@ -16,8 +16,8 @@ KB_N_STAGES = 8
 STAGE_NAMES = ("init", "count", "offsets", "integrate", "histogram", "partition", "reduce", "compress")
 
 # every function declared in include/kbuild.h
-EXPORTS = ("kb_plan", "kb_build_lower_csr", "kb_integrate_lower", "kb_assemble_lower_csr", "kb_status_string",
-           "kb_version")
+EXPORTS = ("kb_plan", "kb_build_lower_csr", "kb_integrate_lower", "kb_assemble_lower_csr", "kb_plan_batched",
+           "kb_build_lower_csr_batched", "kb_status_string", "kb_version")
 
 
 class KbMesh(ctypes.Structure):
@@ -26,6 +26,20 @@ class KbMesh(ctypes.Structure):
         ("reserved", ctypes.c_int32),
         ("n_elem", ctypes.c_int64),
         ("n_node", ctypes.c_int64),
+        ("conn", ctypes.c_void_p),
+        ("coords", ctypes.c_void_p),
+        ("coef", ctypes.c_void_p),
+    ]
+
+
+class KbBatch(ctypes.Structure):
+    _fields_ = [
+        ("elem", ctypes.c_int32),
+        ("n_mesh", ctypes.c_int32),
+        ("n_elem", ctypes.c_int64),
+        ("n_node", ctypes.c_int64),
+        ("elem_off", ctypes.c_void_p),
+        ("node_off", ctypes.c_void_p),
         ("conn", ctypes.c_void_p),
         ("coords", ctypes.c_void_p),
         ("coef", ctypes.c_void_p),
@@ -64,6 +78,11 @@ def lib():
         L.kb_integrate_lower.restype = i32
         L.kb_assemble_lower_csr.argtypes = [PM, i32, PT, p, p, sz, p, p, p, i64, p, p, p]
         L.kb_assemble_lower_csr.restype = i32
+        PB = ctypes.POINTER(KbBatch)
+        L.kb_plan_batched.argtypes = [PB, i32, PT, ctypes.POINTER(sz), ctypes.POINTER(i64)]
+        L.kb_plan_batched.restype = i32
+        L.kb_build_lower_csr_batched.argtypes = [PB, i32, PT, p, sz, p, p, p, i64, p, p, p]
+        L.kb_build_lower_csr_batched.restype = i32
         L.kb_status_string.argtypes = [i32]
         L.kb_status_string.restype = ctypes.c_char_p
         L.kb_version.argtypes = []

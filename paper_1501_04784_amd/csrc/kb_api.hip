@@ -10,6 +10,7 @@
 #include <atomic>
 
 #include "kb_assemble.hpp"
+#include "kb_batch.hpp"
 #include "kb_kernels.hpp"
 #include "kbuild.h"
 
@@ -448,6 +449,37 @@ int dispatch_integrate(const Plan& p, const kb_mesh* m, void* vals, uint32_t* st
   }
 }
 
+// the batch as one mesh (its connectivity replaced by the shifted copy at launch)
+int batch_as_mesh(const kb_batch* b, kb_mesh* m) {
+  if (!b || b->n_mesh < 0) return KB_EINVAL;
+  *m = kb_mesh{b->elem, 0, b->n_elem, b->n_node, b->conn, b->coords, b->coef};
+  return KB_OK;
+}
+
+// batch workspace: the pipeline's, then the shifted connectivity, the batch CSR row
+// pointers and one flag word
+struct BatchPlan {
+  Plan p;
+  size_t o_gconn = 0, o_uptr = 0, o_flags = 0, total = 0;
+};
+
+int make_batch_plan(const kb_batch* b, int prec, const kb_tuning* tu, BatchPlan* bp) {
+  kb_mesh m;
+  KB_TRY(batch_as_mesh(b, &m));
+  KB_TRY(make_plan(&m, prec, tu, &bp->p));
+  size_t off = bp->p.total;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + (bytes > 0 ? bytes : 1));
+    return o;
+  };
+  bp->o_gconn = take(4 * (size_t)bp->p.nen * (size_t)bp->p.nel);
+  bp->o_uptr = take(4 * ((size_t)bp->p.nn + 1));
+  bp->o_flags = take(4);
+  bp->total = off;
+  return KB_OK;
+}
+
 int check_mesh_ptrs(const kb_mesh* m, bool need_geometry) {
   if ((m->n_elem > 0 && !m->conn)) return KB_EINVAL;
   if (need_geometry && m->n_elem > 0 && (!m->coords || !m->coef)) return KB_EINVAL;
@@ -518,6 +550,70 @@ int kb_assemble_lower_csr(const kb_mesh* mesh, int prec, const kb_tuning* tuning
   static const double kEmpty = 0.0;
   return build_common(mesh, prec, tuning, klow ? klow : (const void*)&kEmpty, ws, ws_bytes, row_ptr, col_idx, vals,
                       cap, nnz_dev, status_dev, stream);
+}
+
+int kb_plan_batched(const kb_batch* batch, int prec, const kb_tuning* tuning, size_t* ws_bytes,
+                    int64_t* n_triplets) {
+  BatchPlan bp;
+  KB_TRY(make_batch_plan(batch, prec, tuning, &bp));
+  if (ws_bytes) *ws_bytes = bp.total;
+  if (n_triplets) *n_triplets = bp.p.T;
+  return KB_OK;
+}
+
+int kb_build_lower_csr_batched(const kb_batch* batch, int prec, const kb_tuning* tuning, void* ws, size_t ws_bytes,
+                               int32_t* row_ptr, int32_t* col_idx, void* vals, int64_t cap, int64_t* nnz_off,
+                               uint32_t* status_dev, void* stream) {
+  BatchPlan bp;
+  KB_TRY(make_batch_plan(batch, prec, tuning, &bp));
+  Plan& p = bp.p;
+  kb_mesh m;
+  KB_TRY(batch_as_mesh(batch, &m));
+  KB_TRY(check_mesh_ptrs(&m, true));
+  if (!batch->elem_off || !batch->node_off || !row_ptr || !nnz_off || !status_dev || cap < 0) return KB_EINVAL;
+  if (cap > 0 && (!col_idx || !vals)) return KB_EINVAL;
+  if (ws_bytes < bp.total) return KB_ENOSPC;
+  if (!ws) return KB_EINVAL;
+  KB_TRY(device_cus(&p.cus));
+  auto* w = (unsigned char*)ws;
+  auto s = (hipStream_t)stream;
+  auto* gconn = (int32_t*)(w + bp.o_gconn);
+  auto* uptr = (int32_t*)(w + bp.o_uptr);
+  auto* flags = (uint32_t*)(w + bp.o_flags);
+  const int64_t nm = batch->n_mesh;
+  k_fill_i32<<<1, 64, 0, s>>>((int32_t*)flags, 1, 0);
+  KB_LAUNCH_CHECK();
+  k_batch_check<<<grid_for(nm + 1, 256), 256, 0, s>>>(batch->elem_off, batch->node_off, nm, p.nel, p.nn, flags);
+  KB_LAUNCH_CHECK();
+  if (p.nel > 0 && nm > 0) {
+    const unsigned g = (unsigned)std::min<int64_t>(div_up(p.nel, 256), 65536);
+    if (p.nen == 8)
+      k_batch_conn<8><<<g, 256, 0, s>>>(batch->conn, batch->elem_off, batch->node_off, nm, p.nel, gconn);
+    else
+      k_batch_conn<4><<<g, 256, 0, s>>>(batch->conn, batch->elem_off, batch->node_off, nm, p.nel, gconn);
+    KB_LAUNCH_CHECK();
+    m.conn = gconn;
+  }
+  // the batch's matrix: union CSR row pointers into the workspace, entries in place;
+  // nnz_off[n_mesh] receives the total
+  Events ev{tuning ? tuning->stage_events : nullptr, s};
+  if (p.nen == 8)
+    KB_TRY(dispatch_build<8>(p, &m, nullptr, w, uptr, col_idx, vals, cap, nnz_off + nm, status_dev, ev, s));
+  else
+    KB_TRY(dispatch_build<4>(p, &m, nullptr, w, uptr, col_idx, vals, cap, nnz_off + nm, status_dev, ev, s));
+  if (nm > 0) {
+    if (p.nn > 0) {
+      k_batch_rows<<<(unsigned)std::min<int64_t>(div_up(p.nn, 256), 65536), 256, 0, s>>>(uptr, batch->node_off, nm,
+                                                                                          p.nn, cap, col_idx, row_ptr);
+      KB_LAUNCH_CHECK();
+    }
+    k_batch_meshes<<<grid_for(nm, 256), 256, 0, s>>>(uptr, batch->node_off, nm, flags, row_ptr, nnz_off, status_dev);
+    KB_LAUNCH_CHECK();
+  } else {
+    k_batch_meshes<<<1, 64, 0, s>>>(uptr, batch->node_off, nm, flags, row_ptr, nnz_off, status_dev);
+    KB_LAUNCH_CHECK();
+  }
+  return KB_OK;
 }
 
 int kb_integrate_lower(const kb_mesh* mesh, int prec, const kb_tuning* tuning, void* vals, uint32_t* status_dev,

@@ -8,7 +8,7 @@ import re
 import pytest
 
 from paper_1501_04784_amd import _lib
-from paper_1501_04784_amd._lib import KbMesh, KbTuning
+from paper_1501_04784_amd._lib import KbBatch, KbMesh, KbTuning
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "kbuild.h")
@@ -127,3 +127,46 @@ def test_build_argument_errors_return_before_any_launch():
     assert L.kb_assemble_lower_csr(ctypes.byref(m), 0, None, None, fake, ws, fake, fake, fake, nt, fake, fake,
                                    None) == _lib.KB_EINVAL
     assert L.kb_integrate_lower(ctypes.byref(m), 0, None, fake, None, None) == _lib.KB_EINVAL
+
+
+def test_batch_struct_layout():
+    assert ctypes.sizeof(KbBatch) == 64
+    assert KbBatch.elem_off.offset == 24 and KbBatch.coef.offset == 56
+
+
+def test_plan_batched_adds_packing_space():
+    L = _lib.lib()
+    b = KbBatch(8, 3, 1000, 1331, None, None, None, None, None)
+    ws, nt = ctypes.c_size_t(0), ctypes.c_int64(0)
+    assert L.kb_plan_batched(ctypes.byref(b), 0, None, ctypes.byref(ws), ctypes.byref(nt)) == 0
+    rc, ws1, nt1 = _plan(8, 1000, 1331)
+    assert nt.value == nt1 and ws.value >= ws1 + 4 * 8 * 1000 + 4 * 1332
+    b.n_mesh = -1
+    assert L.kb_plan_batched(ctypes.byref(b), 0, None, ctypes.byref(ws), ctypes.byref(nt)) == _lib.KB_EINVAL
+    assert L.kb_plan_batched(None, 0, None, None, None) == _lib.KB_EINVAL
+
+
+def test_build_batched_argument_errors():
+    L = _lib.lib()
+    fake = 0x1000
+    b = KbBatch(8, 2, 10, 20, fake, fake, fake, fake, fake)
+    ws, nt = ctypes.c_size_t(0), ctypes.c_int64(0)
+    assert L.kb_plan_batched(ctypes.byref(b), 0, None, ctypes.byref(ws), ctypes.byref(nt)) == 0
+    f = ctypes.c_void_p(fake)
+
+    def call(**kw):
+        a = dict(ws=f, wsb=ws.value, rp=f, col=f, val=f, cap=nt.value, off=f, st=f)
+        a.update(kw)
+        return L.kb_build_lower_csr_batched(ctypes.byref(b), 0, None, a["ws"], a["wsb"], a["rp"], a["col"], a["val"],
+                                            a["cap"], a["off"], a["st"], None)
+
+    assert call(wsb=ws.value - 1) == _lib.KB_ENOSPC
+    assert call(rp=None) == _lib.KB_EINVAL
+    assert call(off=None) == _lib.KB_EINVAL
+    assert call(st=None) == _lib.KB_EINVAL
+    assert call(ws=None) == _lib.KB_EINVAL
+    b.elem_off = None
+    assert call() == _lib.KB_EINVAL
+    b.elem_off = fake
+    b.coords = None
+    assert call() == _lib.KB_EINVAL
