@@ -39,6 +39,8 @@ def lib():
         L.orc_build_lower_csr.restype = i64
         L.orc_rows_lower.argtypes = [i32, i64, i64, p, p, p, i64, p, p, p, p, i64]
         L.orc_rows_lower.restype = i64
+        L.orc_adjoint_lower.argtypes = [i32, i64, i64, p, p, p, p, p, p, p, p]
+        L.orc_adjoint_lower.restype = i64
         _lib = L
     return _lib
 
@@ -144,3 +146,17 @@ def rows_lower(elem, conn, coords, coef, rows):
 
 def build_mesh(mesh):
     return build_lower_csr(mesh.elem, mesh.conn, mesh.coords, mesh.coef)
+
+
+def adjoint_lower(mesh, row_ptr, col_idx, w):
+    """(dL/dc [n_elem], dL/dX [n_node, 3]) of L = sum W_ij K_ij over the lower pattern
+    (row_ptr, col_idx) of the mesh's K, W aligned with that pattern.  FP64."""
+    conn = _c(mesh.conn, np.int32)
+    gc = np.zeros(mesh.n_elem)
+    gx = np.zeros((mesh.n_node, 3))
+    r = lib().orc_adjoint_lower(mesh.elem, mesh.n_elem, mesh.n_node, _p(conn), _p(_c(mesh.coords, np.float64)),
+                                _p(_c(mesh.coef, np.float64)), _p(_c(row_ptr, np.int32)), _p(_c(col_idx, np.int32)),
+                                _p(_c(w, np.float64)), _p(gc), _p(gx))
+    if r < 0:
+        raise ValueError("element pair outside the given pattern")
+    return gc, gx, int(r)

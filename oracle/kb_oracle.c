@@ -410,3 +410,137 @@ int64_t orc_rows_lower(int elem, int64_t n_elem, int64_t n_node, const int32_t* 
   free(slot);
   return n;
 }
+
+/* ---- adjoint of the construction (not in the paper) ---------------------------
+ *
+ * For a loss L = sum over the lower pattern of W_ij K_ij, W given in the layout of
+ * the lower CSR (row_ptr, col_idx) of K, this returns dL/dc (per element) and dL/dX
+ * (per node), in FP64.  Derivation from Eq. 7-9:
+ *   per element, let S (nen x nen, symmetric) have S_aa = W(E_a, E_a) and
+ *   S_ab = S_ba = W(row, col of the pair a, b) / 2 for a != b, so that the element's
+ *   share of L is the Frobenius product S : k_e (each off-diagonal global entry takes
+ *   k_ab once, and S counts it twice at half weight);
+ *   k_e is linear in c, so dL/dc_e = S : k_e / c = sum_q w_q |J_q| tr(B_q S B_q^T);
+ *   with M_q = B_q S B_q^T, d|J| = |J| tr(J^{-1} dJ), d(J^{-1}) = -J^{-1} dJ J^{-1} and
+ *   dJ = dN dX, one gets dL/dX_e = c sum_q w_q |J_q| B_q^T (tr(M_q) I - 2 M_q), a
+ *   nen x 3 block whose row a is added to the gradient of node E_a.
+ * Elements with index errors are skipped.  Returns the OR of their flags, or -1 if an
+ * element pair has no entry in the given pattern (or on a bad argument).
+ */
+
+/* position of (row, col) in the lower CSR, or -1 */
+static int64_t csr_find(const int32_t* row_ptr, const int32_t* col_idx, int32_t row, int32_t col) {
+  int64_t lo = row_ptr[row], hi = (int64_t)row_ptr[row + 1] - 1;
+  while (lo <= hi) {
+    int64_t mid = (lo + hi) / 2;
+    if (col_idx[mid] == col) return mid;
+    if (col_idx[mid] < col)
+      lo = mid + 1;
+    else
+      hi = mid - 1;
+  }
+  return -1;
+}
+
+/* one integration point of the adjoint: adds w |J| tr(M) to *gc and
+ * c w |J| B^T (tr(M) I - 2M) to G (nen x 3) */
+static void adjoint_point(int nen, const double dN[3][8], const double X[][3], const double S[8][8], double W,
+                          double c, double* gc, double G[8][3]) {
+  double J[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0.0;
+      for (int a = 0; a < nen; ++a) s += dN[i][a] * X[a][j];
+      J[i][j] = s;
+    }
+  double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1])
+             - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0])
+             + J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+  double Ji[3][3];
+  Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
+  Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+  Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+  Ji[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
+  Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+  Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+  Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
+  Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+  Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+  double B[3][8];
+  for (int i = 0; i < 3; ++i)
+    for (int a = 0; a < nen; ++a) {
+      double s = 0.0;
+      for (int j = 0; j < 3; ++j) s += Ji[i][j] * dN[j][a];
+      B[i][a] = s;
+    }
+  /* M = B S B^T */
+  double M[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0.0;
+      for (int a = 0; a < nen; ++a)
+        for (int b = 0; b < nen; ++b) s += B[i][a] * S[a][b] * B[j][b];
+      M[i][j] = s;
+    }
+  double tr = M[0][0] + M[1][1] + M[2][2];
+  *gc += W * det * tr;
+  for (int a = 0; a < nen; ++a)
+    for (int i = 0; i < 3; ++i) {
+      double s = tr * B[i][a];
+      for (int j = 0; j < 3; ++j) s -= 2.0 * B[j][a] * M[j][i];
+      G[a][i] += c * W * det * s;
+    }
+}
+
+int64_t orc_adjoint_lower(int elem, int64_t n_elem, int64_t n_node, const int32_t* conn, const double* coords,
+                          const double* coef, const int32_t* row_ptr, const int32_t* col_idx, const double* w,
+                          double* grad_coef, double* grad_coords) {
+  int nen = elem;
+  if (elem != 8 && elem != 4) return -1;
+  for (int64_t i = 0; i < 3 * n_node; ++i) grad_coords[i] = 0.0;
+  unsigned flags = 0;
+  double gx[5], gw[5];
+  orc_gauss_rule(2, gx, gw);
+  for (int64_t e = 0; e < n_elem; ++e) {
+    const int32_t* E = conn + e * nen;
+    grad_coef[e] = 0.0;
+    unsigned f = check_element(nen, E, n_node);
+    if (f) {
+      flags |= f;
+      continue;
+    }
+    double X[8][3], S[8][8], G[8][3];
+    for (int a = 0; a < nen; ++a)
+      for (int j = 0; j < 3; ++j) {
+        X[a][j] = coords[(int64_t)E[a] * 3 + j];
+        G[a][j] = 0.0;
+      }
+    for (int a = 0; a < nen; ++a)
+      for (int b = 0; b < nen; ++b) {
+        int32_t row = E[a] > E[b] ? E[a] : E[b], col = E[a] > E[b] ? E[b] : E[a];
+        int64_t k = csr_find(row_ptr, col_idx, row, col);
+        if (k < 0) return -1;
+        S[a][b] = a == b ? w[k] : 0.5 * w[k];
+      }
+    double gc = 0.0;
+    if (elem == 8) {
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+          for (int k = 0; k < 2; ++k) {
+            double dN[3][8];
+            hex_dN(gx[i], gx[j], gx[k], dN);
+            adjoint_point(8, dN, X, S, gw[i] * gw[j] * gw[k], coef[e], &gc, G);
+          }
+    } else {
+      double dN4[3][4], dN[3][8];
+      tet_dN(dN4);
+      for (int i = 0; i < 3; ++i)
+        for (int a = 0; a < 4; ++a) dN[i][a] = dN4[i][a];
+      adjoint_point(4, dN, X, S, 1.0 / 6.0, coef[e], &gc, G);
+    }
+    grad_coef[e] = gc;
+    for (int a = 0; a < nen; ++a)
+      for (int j = 0; j < 3; ++j) grad_coords[(int64_t)E[a] * 3 + j] += G[a][j];
+  }
+  return (int64_t)flags;
+}
