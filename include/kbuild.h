@@ -206,6 +206,23 @@ int kb_build_lower_csr_batched(const kb_batch* batch, int prec, const kb_tuning*
                                int32_t* row_ptr, int32_t* col_idx, void* vals, int64_t cap, int64_t* nnz_off,
                                uint32_t* status_dev, void* stream);
 
+/*
+ * Adjoint (not part of the paper; derived from Eq. 7-9).  For the loss
+ * L = sum over the lower pattern of w_ij K_ij, with w (device double [nnz]) laid out
+ * like the values of the lower CSR (row_ptr, col_idx) that kb_build_lower_csr produced
+ * for this mesh, writes
+ *   grad_coef   device double [n_elem]     dL/dc_e,
+ *   grad_coords device double [n_node][3]  dL/dX (x, y, z of each node).
+ * All arithmetic is FP64 whatever precision built K.  Node gradients are summed exactly
+ * (fixed-point integers), so the output is bitwise deterministic; exact while no node
+ * belongs to more than 65,536 elements.  A node pair of an element that is missing
+ * from the pattern sets KB_F_INDEX (its weight is taken as 0); elements with index
+ * errors contribute nothing.  Workspace from kb_plan_adjoint (host only).
+ */
+int kb_plan_adjoint(const kb_mesh* mesh, size_t* ws_bytes);
+int kb_adjoint_lower(const kb_mesh* mesh, const int32_t* row_ptr, const int32_t* col_idx, const double* w, void* ws,
+                     size_t ws_bytes, double* grad_coef, double* grad_coords, uint32_t* status_dev, void* stream);
+
 /* Static text for a return code (negative) or a single status flag bit (positive). */
 const char* kb_status_string(int code);
 

@@ -228,6 +228,57 @@ def integrate_lower(conn, coords, coef, elem: int, prec="fp64", tuning: Tuning |
     return out, status
 
 
+# ---- adjoint ---------------------------------------------------------------------------
+def adjoint_lower(conn, coords, coef, elem: int, row_ptr, col_idx, w, check=True, allow_flags: int = 0):
+    """(dL/dc [n_elem], dL/dX [n_node, 3]) of L = sum w_ij K_ij over the lower pattern
+    (row_ptr, col_idx) of this mesh's K, w (float64) aligned with that pattern.  FP64."""
+    _validate_mesh(conn, coords, coef, elem)
+    if w.dtype != torch.float64 or w.numel() != col_idx.numel() or not w.is_contiguous():
+        raise ValueError("w must be a contiguous float64 tensor with one weight per pattern entry")
+    m = _mesh(elem, conn.shape[0], coords.shape[0], conn, coords, coef)
+    L = _lib.lib()
+    ws_bytes = ctypes.c_size_t(0)
+    _check(L.kb_plan_adjoint(ctypes.byref(m), ctypes.byref(ws_bytes)), "kb_plan_adjoint")
+    ws = torch.empty(max(int(ws_bytes.value), 1), dtype=torch.uint8, device=conn.device)
+    gc = torch.empty(conn.shape[0], dtype=torch.float64, device=conn.device)
+    gx = torch.empty((coords.shape[0], 3), dtype=torch.float64, device=conn.device)
+    status = torch.zeros(KB_STATUS_WORDS, dtype=torch.int32, device=conn.device)
+    rc = L.kb_adjoint_lower(ctypes.byref(m), _ptr(row_ptr), _ptr(col_idx), _ptr(w), _ptr(ws), int(ws_bytes.value),
+                            _ptr(gc), _ptr(gx), _ptr(status), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    _check(rc, "kb_adjoint_lower")
+    if check:
+        torch.cuda.current_stream().synchronize()
+        _raise_on_flags(int(status[0].item()) & 0xFFFFFFFF, allow_flags)
+    return gc, gx
+
+
+class _LowerK(torch.autograd.Function):
+    """Values of lower-triangular CSR K as a differentiable function of (coords, coef)."""
+
+    @staticmethod
+    def forward(ctx, coords, coef, conn, elem):
+        r = build_lower_csr(conn, coords, coef, elem, prec="fp64")
+        row_ptr, col_idx = r.row_ptr.clone(), r.col_idx.clone()
+        ctx.save_for_backward(coords, coef, conn, row_ptr, col_idx)
+        ctx.elem = elem
+        ctx.mark_non_differentiable(row_ptr, col_idx)
+        return r.vals.clone(), row_ptr, col_idx
+
+    @staticmethod
+    def backward(ctx, g_vals, _g_row_ptr, _g_col_idx):
+        coords, coef, conn, row_ptr, col_idx = ctx.saved_tensors
+        if g_vals is None:
+            return None, None, None, None
+        gc, gx = adjoint_lower(conn, coords, coef, ctx.elem, row_ptr, col_idx, g_vals.contiguous().to(torch.float64))
+        return (gx if ctx.needs_input_grad[0] else None), (gc if ctx.needs_input_grad[1] else None), None, None
+
+
+def lower_csr_values(coords, coef, conn, elem: int):
+    """(vals, row_ptr, col_idx) of lower CSR K in FP64; vals is differentiable in coords and
+    coef through the adjoint kernel (backward of any loss that is a function of vals)."""
+    return _LowerK.apply(coords, coef, conn, elem)
+
+
 # ---- batches -------------------------------------------------------------------------
 @dataclass
 class Batch:
@@ -383,6 +434,7 @@ def default_candidates(elem: int, prec="fp32fb64"):
 
 
 __all__ = ["Builder", "BatchBuilder", "Batch", "LowerCSR", "KBuildError", "Tuning", "build_lower_csr",
-           "build_lower_csr_batched", "assemble_lower_csr", "integrate_lower", "pack_batch", "plan", "plan_batched",
+           "build_lower_csr_batched", "assemble_lower_csr", "integrate_lower", "adjoint_lower", "lower_csr_values",
+           "pack_batch", "plan", "plan_batched",
            "autotune", "default_candidates", "status_string", "version", "value_dtype", "STAGE_NAMES", "KB_N_STAGES",
            "KB_HEX8", "KB_TET4", "KB_FP64", "KB_FP32", "KB_FP32_FB64"]

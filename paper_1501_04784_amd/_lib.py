@@ -17,7 +17,7 @@ STAGE_NAMES = ("init", "count", "offsets", "integrate", "histogram", "partition"
 
 # every function declared in include/kbuild.h
 EXPORTS = ("kb_plan", "kb_build_lower_csr", "kb_integrate_lower", "kb_assemble_lower_csr", "kb_plan_batched",
-           "kb_build_lower_csr_batched", "kb_status_string", "kb_version")
+           "kb_build_lower_csr_batched", "kb_plan_adjoint", "kb_adjoint_lower", "kb_status_string", "kb_version")
 
 
 class KbMesh(ctypes.Structure):
@@ -83,6 +83,10 @@ def lib():
         L.kb_plan_batched.restype = i32
         L.kb_build_lower_csr_batched.argtypes = [PB, i32, PT, p, sz, p, p, p, i64, p, p, p]
         L.kb_build_lower_csr_batched.restype = i32
+        L.kb_plan_adjoint.argtypes = [PM, ctypes.POINTER(sz)]
+        L.kb_plan_adjoint.restype = i32
+        L.kb_adjoint_lower.argtypes = [PM, p, p, p, p, sz, p, p, p, p]
+        L.kb_adjoint_lower.restype = i32
         L.kb_status_string.argtypes = [i32]
         L.kb_status_string.restype = ctypes.c_char_p
         L.kb_version.argtypes = []

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <atomic>
 
+#include "kb_adjoint.hpp"
 #include "kb_assemble.hpp"
 #include "kb_batch.hpp"
 #include "kb_kernels.hpp"
@@ -611,6 +612,79 @@ int kb_build_lower_csr_batched(const kb_batch* batch, int prec, const kb_tuning*
     KB_LAUNCH_CHECK();
   } else {
     k_batch_meshes<<<1, 64, 0, s>>>(uptr, batch->node_off, nm, flags, row_ptr, nnz_off, status_dev);
+    KB_LAUNCH_CHECK();
+  }
+  return KB_OK;
+}
+
+// adjoint workspace: element gradients, node accumulators, one exponent word
+static int adjoint_layout(const kb_mesh* m, size_t* gel, size_t* acc, size_t* emax, size_t* total) {
+  if (!m) return KB_EINVAL;
+  if (m->elem != KB_HEX8 && m->elem != KB_TET4) return KB_EINVAL;
+  if (m->n_elem < 0 || m->n_node < 0 || m->reserved != 0) return KB_EINVAL;
+  if (m->n_node >= (int64_t)INT32_MAX || m->n_elem > (int64_t)INT32_MAX / m->elem) return KB_ERANGE;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + (bytes > 0 ? bytes : 1));
+    return o;
+  };
+  *gel = take(8 * 3 * (size_t)m->elem * (size_t)m->n_elem);
+  *acc = take(16 * 3 * (size_t)m->n_node);
+  *emax = take(4);
+  *total = off;
+  return KB_OK;
+}
+
+int kb_plan_adjoint(const kb_mesh* mesh, size_t* ws_bytes) {
+  size_t a, b, c, t;
+  KB_TRY(adjoint_layout(mesh, &a, &b, &c, &t));
+  if (ws_bytes) *ws_bytes = t;
+  return KB_OK;
+}
+
+int kb_adjoint_lower(const kb_mesh* mesh, const int32_t* row_ptr, const int32_t* col_idx, const double* w, void* ws,
+                     size_t ws_bytes, double* grad_coef, double* grad_coords, uint32_t* status_dev, void* stream) {
+  size_t o_gel, o_acc, o_emax, total;
+  KB_TRY(adjoint_layout(mesh, &o_gel, &o_acc, &o_emax, &total));
+  KB_TRY(check_mesh_ptrs(mesh, true));
+  if (!status_dev || !ws) return KB_EINVAL;
+  if (ws_bytes < total) return KB_ENOSPC;
+  if (mesh->n_elem > 0 && (!row_ptr || !col_idx || !w || !grad_coef)) return KB_EINVAL;
+  if (mesh->n_node > 0 && !grad_coords) return KB_EINVAL;
+  auto s = (hipStream_t)stream;
+  auto* wsb = (unsigned char*)ws;
+  auto* gel = (double*)(wsb + o_gel);
+  auto* acc = (unsigned long long*)(wsb + o_acc);
+  auto* emax = (uint32_t*)(wsb + o_emax);
+  const int64_t nel = mesh->n_elem, nn = mesh->n_node, nen = mesh->elem;
+  k_init_status<<<1, 64, 0, s>>>(status_dev, nullptr);
+  KB_LAUNCH_CHECK();
+  k_fill_i32<<<1, 64, 0, s>>>((int32_t*)emax, 1, 0);
+  KB_LAUNCH_CHECK();
+  if (nn > 0) {
+    k_fill_u64<<<(unsigned)std::min<int64_t>(div_up(6 * nn, 256), 65536), 256, 0, s>>>(acc, 6 * nn);
+    KB_LAUNCH_CHECK();
+  }
+  if (nel > 0) {
+    const unsigned ge = grid_for(nel, 128);
+    if (nen == 8)
+      k_adjoint_elems<8><<<ge, 128, 0, s>>>(mesh->conn, mesh->coords, mesh->coef, nel, nn, row_ptr, col_idx, w,
+                                            grad_coef, gel, emax, status_dev);
+    else
+      k_adjoint_elems<4><<<ge, 128, 0, s>>>(mesh->conn, mesh->coords, mesh->coef, nel, nn, row_ptr, col_idx, w,
+                                            grad_coef, gel, emax, status_dev);
+    KB_LAUNCH_CHECK();
+    const unsigned gs = (unsigned)std::min<int64_t>(div_up(nel * nen, 256), 65536);
+    if (nen == 8)
+      k_adjoint_scatter<8><<<gs, 256, 0, s>>>(mesh->conn, nel, nn, gel, emax, acc);
+    else
+      k_adjoint_scatter<4><<<gs, 256, 0, s>>>(mesh->conn, nel, nn, gel, emax, acc);
+    KB_LAUNCH_CHECK();
+  }
+  if (nn > 0) {
+    k_adjoint_nodes<<<(unsigned)std::min<int64_t>(div_up(3 * nn, 256), 65536), 256, 0, s>>>(acc, 3 * nn, emax,
+                                                                                            grad_coords);
     KB_LAUNCH_CHECK();
   }
   return KB_OK;

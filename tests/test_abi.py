@@ -170,3 +170,25 @@ def test_build_batched_argument_errors():
     b.elem_off = fake
     b.coords = None
     assert call() == _lib.KB_EINVAL
+
+
+def test_plan_adjoint_and_argument_errors():
+    L = _lib.lib()
+    m = KbMesh(8, 0, 100, 200, 0x1000, 0x1000, 0x1000)
+    ws = ctypes.c_size_t(0)
+    assert L.kb_plan_adjoint(ctypes.byref(m), ctypes.byref(ws)) == 0
+    assert ws.value >= 8 * 3 * 8 * 100 + 16 * 3 * 200
+    assert L.kb_plan_adjoint(None, ctypes.byref(ws)) == _lib.KB_EINVAL
+    f = ctypes.c_void_p(0x1000)
+
+    def call(**kw):
+        a = dict(rp=f, col=f, w=f, ws=f, wsb=ws.value, gc=f, gx=f, st=f)
+        a.update(kw)
+        return L.kb_adjoint_lower(ctypes.byref(m), a["rp"], a["col"], a["w"], a["ws"], a["wsb"], a["gc"], a["gx"],
+                                  a["st"], None)
+
+    assert call(wsb=ws.value - 1) == _lib.KB_ENOSPC
+    for k in ("rp", "col", "w", "ws", "gc", "gx", "st"):
+        assert call(**{k: None}) == _lib.KB_EINVAL, k
+    bad = KbMesh(5, 0, 100, 200, 0x1000, 0x1000, 0x1000)
+    assert L.kb_plan_adjoint(ctypes.byref(bad), ctypes.byref(ws)) == _lib.KB_EINVAL
