@@ -115,6 +115,8 @@ def parse():
     ap.add_argument("--profile-steps", action="store_true", help="no stage events (for profiler runs)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="also time the adjoint (dL/dc, dL/dX of L = sum W K, seeded N(0,1) weights), FP64")
     ap.add_argument("--block", type=int, default=0, help="tuning: element tile / block size")
     ap.add_argument("--bucket-bits", type=int, default=0, help="tuning: log2 rows per first-level bucket")
     ap.add_argument("--sub-bits", type=int, default=0, help="tuning: log2 rows per sub-bucket")
@@ -159,6 +161,29 @@ def time_builds(kb, torch, mesh_dev, m, prec, steps, warmup, stage_events=True, 
     if isinstance(res, list):  # a batch: totals over its meshes
         res = BatchTotals(sum(r.nnz for r in res), res[0].n_fallback if res else 0)
     return ms, wall / steps * 1e3, stages, res
+
+
+def time_adjoint(kb, torch, mesh_dev, m, steps, warmup):
+    """Backward of L = sum W_ij K_ij (FP64 forward pattern, seeded N(0,1) weights)."""
+    import meshgen
+
+    conn, coords, coef = mesh_dev
+    r = kb.build_lower_csr(conn, coords, coef, m.elem, prec="fp64")
+    rp, col = r.row_ptr.clone(), r.col_idx.clone()
+    w = torch.from_numpy(meshgen.loss_weights(r.nnz)).to(conn.device)
+    for _ in range(warmup):
+        kb.adjoint_lower(conn, coords, coef, m.elem, rp, col, w, check=False)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(steps):
+        kb.adjoint_lower(conn, coords, coef, m.elem, rp, col, w, check=False)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    return {"ms_per_step": ms, "value": m.n_elem / (ms * 1e-3), "unit": "elements/s",
+            "note": "includes the workspace and output allocation of each call"}
 
 
 class BatchTotals:
@@ -266,6 +291,9 @@ def main():
         out["fp64"] = {"ms_per_step": ms64, "value": m.n_elem / (ms64 * 1e-3)}
         out["speedup_vs_fp64"] = ms64 / ms
         print(f"[bench] fp64: {ms64:.3f} ms/step", file=sys.stderr, flush=True)
+    if args.adjoint and cid != 4:
+        out["adjoint"] = time_adjoint(kb, torch, mesh_dev, m, args.steps, args.warmup)
+        print(f"[bench] adjoint: {out['adjoint']['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
     if not args.no_cpu:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(meshes if cid == 4 else m, args.cpu_sample)
