@@ -39,6 +39,10 @@ def lib():
         L.orc_build_lower_csr.restype = i64
         L.orc_rows_lower.argtypes = [i32, i64, i64, p, p, p, i64, p, p, p, p, i64]
         L.orc_rows_lower.restype = i64
+        L.orc_element_mass_lower.argtypes = [i32, p, ctypes.c_double, p]
+        L.orc_element_mass_lower.restype = i32
+        L.orc_integrate_mass_lower.argtypes = [i32, i64, i64, p, p, p, p]
+        L.orc_integrate_mass_lower.restype = i64
         L.orc_adjoint_lower.argtypes = [i32, i64, i64, p, p, p, p, p, p, p, p]
         L.orc_adjoint_lower.restype = i64
         _lib = L
@@ -160,3 +164,31 @@ def adjoint_lower(mesh, row_ptr, col_idx, w):
     if r < 0:
         raise ValueError("element pair outside the given pattern")
     return gc, gx, int(r)
+
+
+def element_mass_lower(elem: int, X, rho: float = 1.0):
+    """Packed lower triangle of one element's consistent mass matrix and its flags."""
+    X = _c(X, np.float64)
+    out = np.zeros(elem * (elem + 1) // 2)
+    f = lib().orc_element_mass_lower(elem, _p(X), float(rho), _p(out))
+    if f < 0:
+        raise ValueError("bad element")
+    return out, int(f)
+
+
+def integrate_mass_lower(elem, conn, coords, coef):
+    conn = _c(conn, np.int32)
+    T = elem * (elem + 1) // 2
+    out = np.zeros((conn.shape[0], T))
+    f = lib().orc_integrate_mass_lower(elem, conn.shape[0], coords.shape[0], _p(conn), _p(_c(coords, np.float64)),
+                                       _p(_c(coef, np.float64)), _p(out))
+    if f < 0:
+        raise ValueError("bad element type")
+    return out, int(f)
+
+
+def build_mass_mesh(mesh):
+    """Lower CSR of the consistent mass matrix: element values, then the oracle assembly."""
+    mlow, f = integrate_mass_lower(mesh.elem, mesh.conn, mesh.coords, mesh.coef)
+    rp, col, val, f2 = assemble_lower_csr(mesh.elem, mesh.conn, mesh.n_node, mlow)
+    return rp, col, val, f | f2

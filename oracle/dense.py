@@ -84,3 +84,49 @@ def to_lower_csr(K: np.ndarray, P: np.ndarray):
     row_ptr = np.zeros(K.shape[0] + 1, np.int64)
     np.add.at(row_ptr, rows + 1, 1)
     return np.cumsum(row_ptr).astype(np.int32), cols.astype(np.int32), K[rows, cols]
+
+
+# ---- consistent mass matrix (second route) ---------------------------------------------
+def hex_mass_full(X: np.ndarray, rho: float = 1.0, n: int = 2) -> np.ndarray:
+    """Full 8x8 brick mass matrix rho * int N N^T dV with an n^3 Gauss rule."""
+    g, w = np.polynomial.legendre.leggauss(n)
+    M = np.zeros((8, 8))
+    i, j, k = _HEX_IJK[:, 0], _HEX_IJK[:, 1], _HEX_IJK[:, 2]
+    for a_, r in enumerate(g):
+        for b_, s in enumerate(g):
+            for c_, t in enumerate(g):
+                vr, dr = _lagrange1(np.array(r))
+                vs, ds = _lagrange1(np.array(s))
+                vt, dt = _lagrange1(np.array(t))
+                N = vr[i] * vs[j] * vt[k]
+                dN = np.stack([dr[i] * vs[j] * vt[k], vr[i] * ds[j] * vt[k], vr[i] * vs[j] * dt[k]])
+                J = np.einsum("ia,aj->ij", dN, X)
+                M += w[a_] * w[b_] * w[c_] * np.linalg.det(J) * np.outer(N, N)
+    return rho * M
+
+
+def tet_mass_full(X: np.ndarray, rho: float = 1.0, n: int = 4) -> np.ndarray:
+    """Full 4x4 tet mass matrix by a collapsed-coordinate (Duffy) Gauss rule on the
+    reference tet, r = u, s = v (1 - u), t = w (1 - u)(1 - v), Jacobian (1 - u)^2 (1 - v),
+    scaled by the affine map's determinant."""
+    g, wt = np.polynomial.legendre.leggauss(n)
+    x, wx = (g + 1) / 2, wt / 2  # on [0, 1]
+    M = np.zeros((4, 4))
+    for iu, u in enumerate(x):
+        for iv, v in enumerate(x):
+            for iw, w_ in enumerate(x):
+                r, s, t = u, v * (1 - u), w_ * (1 - u) * (1 - v)
+                N = np.array([1 - r - s - t, r, s, t])
+                M += wx[iu] * wx[iv] * wx[iw] * (1 - u) ** 2 * (1 - v) * np.outer(N, N)
+    D = np.linalg.det((X[1:] - X[0]).T)
+    return rho * D * M
+
+
+def dense_M(elem: int, conn: np.ndarray, coords: np.ndarray, coef: np.ndarray) -> np.ndarray:
+    nn = coords.shape[0]
+    M = np.zeros((nn, nn))
+    for e in range(conn.shape[0]):
+        E = conn[e]
+        me = hex_mass_full(coords[E], coef[e]) if elem == 8 else tet_mass_full(coords[E], coef[e])
+        M[np.ix_(E, E)] += me
+    return M

@@ -544,3 +544,92 @@ int64_t orc_adjoint_lower(int elem, int64_t n_elem, int64_t n_node, const int32_
   }
   return (int64_t)flags;
 }
+
+/* ---- consistent mass matrix (the closing remark of Section 5) -------------------
+ *
+ * The same construction with another integrand: m_ab = rho * integral over the element
+ * of N_a N_b (rho = the element's coefficient), lower triangle, packed as klow.
+ *   Brick: the 2x2x2 Gauss rule of the stiffness matrix, m_ab = rho sum_q |J_q| N_a N_b
+ *   at the points (exact for affine bricks: N_a N_b is tri-quadratic in r, s, t).
+ *   Tet: the exact integral of the product of two barycentric coordinates,
+ *   V (1 + delta_ab) / 20 with V = |J| / 6 (no rule needed).
+ * Returns flag bits (ORC_F_INVERTED, ORC_F_NONFINITE) or -1 on a bad argument.
+ */
+int orc_element_mass_lower(int elem, const double* Xflat, double rho, double* mlow) {
+  int nen = elem;
+  if (elem != 8 && elem != 4) return -1;
+  const double(*X)[3] = (const double(*)[3])Xflat;
+  int T = nen * (nen + 1) / 2;
+  for (int p = 0; p < T; ++p) mlow[p] = 0.0;
+  unsigned flags = 0;
+  for (int a = 0; a < nen; ++a)
+    for (int j = 0; j < 3; ++j)
+      if (!isfinite(X[a][j])) flags |= ORC_F_NONFINITE;
+  if (!isfinite(rho)) flags |= ORC_F_NONFINITE;
+  if (elem == 8) {
+    double gx[5], gw[5];
+    orc_gauss_rule(2, gx, gw);
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j)
+        for (int k = 0; k < 2; ++k) {
+          double r = gx[i], s = gx[j], t = gx[k], dN[3][8], N[8], J[3][3];
+          hex_dN(r, s, t, dN);
+          for (int a = 0; a < 8; ++a)
+            N[a] = (1.0 + HEX_NAT[a][0] * r) * (1.0 + HEX_NAT[a][1] * s) * (1.0 + HEX_NAT[a][2] * t) / 8.0;
+          for (int p = 0; p < 3; ++p)
+            for (int q = 0; q < 3; ++q) {
+              double acc = 0.0;
+              for (int a = 0; a < 8; ++a) acc += dN[p][a] * X[a][q];
+              J[p][q] = acc;
+            }
+          double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1])
+                     - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0])
+                     + J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+          if (!(det > 0.0)) flags |= ORC_F_INVERTED;
+          double W = gw[i] * gw[j] * gw[k];
+          for (int a = 0; a < 8; ++a)
+            for (int b = 0; b <= a; ++b) mlow[a * (a + 1) / 2 + b] += W * det * N[a] * N[b];
+        }
+  } else {
+    double J[3][3];
+    for (int p = 0; p < 3; ++p)
+      for (int q = 0; q < 3; ++q) J[p][q] = X[p + 1][q] - X[0][q];
+    double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1])
+               - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0])
+               + J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    if (!(det > 0.0)) flags |= ORC_F_INVERTED;
+    double V = det / 6.0;
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b <= a; ++b) mlow[a * (a + 1) / 2 + b] = V * (a == b ? 2.0 : 1.0) / 20.0;
+  }
+  for (int p = 0; p < T; ++p) {
+    mlow[p] *= rho;
+    if (!isfinite(mlow[p])) flags |= ORC_F_NONFINITE;
+  }
+  return (int)flags;
+}
+
+/* Mass values of every element, element-major (as orc_integrate_lower). */
+int64_t orc_integrate_mass_lower(int elem, int64_t n_elem, int64_t n_node, const int32_t* conn,
+                                 const double* coords, const double* coef, double* out) {
+  int nen = elem;
+  if (elem != 8 && elem != 4) return -1;
+  int T = nen * (nen + 1) / 2;
+  unsigned flags = 0;
+  double X[8][3];
+  for (int64_t e = 0; e < n_elem; ++e) {
+    const int32_t* E = conn + e * nen;
+    unsigned f = check_element(nen, E, n_node);
+    if (f) {
+      flags |= f;
+      for (int p = 0; p < T; ++p) out[e * T + p] = 0.0;
+      continue;
+    }
+    for (int a = 0; a < nen; ++a)
+      for (int j = 0; j < 3; ++j) X[a][j] = coords[(int64_t)E[a] * 3 + j];
+    int r = orc_element_mass_lower(elem, &X[0][0], coef[e], out + e * T);
+    if (r < 0) return -1;
+    flags |= (unsigned)r;
+  }
+  return (int64_t)flags;
+}

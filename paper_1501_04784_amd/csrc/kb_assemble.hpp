@@ -729,7 +729,6 @@ __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* _
   __shared__ unsigned long long s_lo[HT];  // sum of low 48-bit chunks
   __shared__ unsigned long long s_hi[HT];  // sum of signed high chunks
   __shared__ uint16_t s_slot[HT];  // occupied slots, in insertion order
-  __shared__ uint16_t s_w[HT];     // index of each occupied slot within its row
   __shared__ uint32_t s_lcol[HT];  // columns of the occupied slots, grouped by row
   __shared__ uint32_t s_rc[256];   // entries per row
   __shared__ uint32_t s_ro[256];   // row offsets
@@ -820,16 +819,25 @@ __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* _
   }
   // order the U entries by (row, col): count per row, scan, group by row, rank by col
   const uint32_t U = s_nu;
-  for (uint32_t f = threadIdx.x; f < U; f += NT)
-    s_w[f] = (uint16_t)atomicAdd(&s_rc[s_key[s_slot[f]] >> colbits], 1u);
+  constexpr int KMAX = HT / NT;  // entries per thread at most
+  uint32_t wi[KMAX];             // each entry's index within its row
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) {
+    const uint32_t f = threadIdx.x + q * NT;
+    if (f < U) wi[q] = atomicAdd(&s_rc[s_key[s_slot[f]] >> colbits], 1u);
+  }
   __syncthreads();
   const int RB = 1 << s2;  // rows of a full sub-bucket (<= 256)
   for (int r = threadIdx.x; r < RB; r += NT) s_ro[r] = s_rc[r];
   __syncthreads();
   block_scan_array(s_ro, RB, s_scan);
-  for (uint32_t f = threadIdx.x; f < U; f += NT) {
-    const uint32_t h = s_slot[f];
-    s_lcol[s_ro[s_key[h] >> colbits] + s_w[f]] = s_key[h] & cmask;
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) {
+    const uint32_t f = threadIdx.x + q * NT;
+    if (f < U) {
+      const uint32_t k = s_key[s_slot[f]];
+      s_lcol[s_ro[k >> colbits] + wi[q]] = k & cmask;
+    }
   }
   __syncthreads();
   for (uint32_t f = threadIdx.x; f < U; f += NT) {
