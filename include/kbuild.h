@@ -98,9 +98,14 @@ extern "C" {
 #define KB_STAGE_REDUCE 6     /* per sub-bucket: group equal (row, col), exact sums         */
 #define KB_STAGE_COMPRESS 7   /* scan of unique counts, row_ptr, col_idx / vals             */
 
+/* element integrands (kb_mesh.op) */
+#define KB_OP_STIFFNESS 0 /* k_ab = c * integral of grad N_a . grad N_b (Eq. 7-9)            */
+#define KB_OP_MASS 1      /* m_ab = c * integral of N_a N_b, the consistent mass matrix
+                             (Section 5): brick 2x2x2 rule, tet exact |J| (1 + delta_ab) / 120 */
+
 typedef struct {
   int32_t elem;          /* KB_HEX8 or KB_TET4                                         */
-  int32_t reserved;      /* must be 0                                                   */
+  int32_t op;            /* KB_OP_STIFFNESS (0) or KB_OP_MASS                           */
   int64_t n_elem;        /* number of elements (>= 0)                                   */
   int64_t n_node;        /* number of nodes = matrix dimension (>= 0)                   */
   const int32_t* conn;   /* device [n_elem][nen] node ids, row-major                    */

@@ -18,9 +18,11 @@ import torch
 
 from . import _lib
 from ._lib import (KB_F_CAPACITY, KB_F_INDEX, KB_F_INVERTED, KB_F_NONFINITE, KB_F_REPEAT, KB_FP32, KB_FP32_FB64,
-                   KB_FP64, KB_HEX8, KB_N_STAGES, KB_STATUS_WORDS, KB_TET4, STAGE_NAMES, KbBatch, KbMesh, KbTuning)
+                   KB_FP64, KB_HEX8, KB_N_STAGES, KB_OP_MASS, KB_OP_STIFFNESS, KB_STATUS_WORDS, KB_TET4, STAGE_NAMES,
+                   KbBatch, KbMesh, KbTuning)
 
 PRECISIONS = {"fp64": KB_FP64, "fp32": KB_FP32, "fp32fb64": KB_FP32_FB64}
+OPERATORS = {"stiffness": KB_OP_STIFFNESS, "mass": KB_OP_MASS}
 FLAG_NAMES = {KB_F_INDEX: "index", KB_F_REPEAT: "repeat", KB_F_INVERTED: "inverted", KB_F_NONFINITE: "nonfinite",
               KB_F_CAPACITY: "capacity"}
 
@@ -58,8 +60,16 @@ def _ptr(t: torch.Tensor | None):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
-def _mesh(elem, n_elem, n_node, conn=None, coords=None, coef=None) -> KbMesh:
-    return KbMesh(int(elem), 0, int(n_elem), int(n_node), None if conn is None else conn.data_ptr(),
+def _op(op) -> int:
+    if isinstance(op, str):
+        return OPERATORS[op]
+    if op in (KB_OP_STIFFNESS, KB_OP_MASS):
+        return int(op)
+    raise ValueError(f"unknown operator {op!r}")
+
+
+def _mesh(elem, n_elem, n_node, conn=None, coords=None, coef=None, op="stiffness") -> KbMesh:
+    return KbMesh(int(elem), _op(op), int(n_elem), int(n_node), None if conn is None else conn.data_ptr(),
                   None if coords is None else coords.data_ptr(), None if coef is None else coef.data_ptr())
 
 
@@ -74,11 +84,11 @@ class Tuning:
         return KbTuning(int(self.block), int(self.bucket_bits), float(self.fb_tau), int(self.sub_bits), events)
 
 
-def plan(elem: int, n_elem: int, n_node: int, prec="fp64", tuning: Tuning | None = None):
+def plan(elem: int, n_elem: int, n_node: int, prec="fp64", tuning: Tuning | None = None, op="stiffness"):
     """(workspace bytes, number of triplets) for a mesh shape."""
     ws = ctypes.c_size_t(0)
     nt = ctypes.c_int64(0)
-    m = _mesh(elem, n_elem, n_node)
+    m = _mesh(elem, n_elem, n_node, op=op)
     tu = (tuning or Tuning()).to_c()
     _check(_lib.lib().kb_plan(ctypes.byref(m), _prec(prec), ctypes.byref(tu), ctypes.byref(ws), ctypes.byref(nt)),
            "kb_plan")
@@ -139,11 +149,12 @@ class Builder:
     """
 
     def __init__(self, elem: int, n_elem: int, n_node: int, prec="fp32fb64", tuning: Tuning | None = None,
-                 device="cuda", cap: int | None = None):
+                 device="cuda", cap: int | None = None, op="stiffness"):
         self.elem, self.n_elem, self.n_node = int(elem), int(n_elem), int(n_node)
         self.prec = _prec(prec)
+        self.op = _op(op)
         self.tuning = tuning or Tuning()
-        self.ws_bytes, self.n_triplets = plan(elem, n_elem, n_node, self.prec, self.tuning)
+        self.ws_bytes, self.n_triplets = plan(elem, n_elem, n_node, self.prec, self.tuning, self.op)
         self.cap = self.n_triplets if cap is None else int(cap)
         dev = torch.device(device)
         self.ws = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=dev)
@@ -162,7 +173,7 @@ class Builder:
             self._ev_keep = arr
             ev = ctypes.cast(arr, ctypes.c_void_p)
         tu = self.tuning.to_c(ev)
-        m = _mesh(self.elem, self.n_elem, self.n_node, conn, coords, coef)
+        m = _mesh(self.elem, self.n_elem, self.n_node, conn, coords, coef, self.op)
         L = _lib.lib()
         if klow is None:
             rc = L.kb_build_lower_csr(ctypes.byref(m), self.prec, ctypes.byref(tu), _ptr(self.ws), self.ws_bytes,
@@ -189,10 +200,11 @@ class Builder:
 
 
 def build_lower_csr(conn, coords, coef, elem: int, prec="fp32fb64", tuning: Tuning | None = None, check=True,
-                    allow_flags: int = 0, cap: int | None = None) -> LowerCSR:
-    """Integrate and assemble lower-triangular CSR K on the GPU (one call)."""
+                    allow_flags: int = 0, cap: int | None = None, op="stiffness") -> LowerCSR:
+    """Integrate and assemble lower-triangular CSR K (or the consistent mass matrix with
+    op="mass") on the GPU (one call)."""
     _validate_mesh(conn, coords, coef, elem)
-    b = Builder(elem, conn.shape[0], coords.shape[0], prec, tuning, device=conn.device, cap=cap)
+    b = Builder(elem, conn.shape[0], coords.shape[0], prec, tuning, device=conn.device, cap=cap, op=op)
     b.run(conn, coords, coef)
     return b.result(check=check, allow_flags=allow_flags)
 
@@ -210,13 +222,13 @@ def assemble_lower_csr(conn, n_node: int, klow, elem: int, prec="fp64", tuning: 
 
 
 def integrate_lower(conn, coords, coef, elem: int, prec="fp64", tuning: Tuning | None = None, check=True,
-                    allow_flags: int = 0):
+                    allow_flags: int = 0, op="stiffness"):
     """Per-element packed lower triangles [n_elem, nen(nen+1)/2] (Alg. 2 only)."""
     _validate_mesh(conn, coords, coef, elem)
     te = elem * (elem + 1) // 2
     out = torch.empty((conn.shape[0], te), dtype=value_dtype(prec), device=conn.device)
     status = torch.zeros(KB_STATUS_WORDS, dtype=torch.int32, device=conn.device)
-    m = _mesh(elem, conn.shape[0], coords.shape[0], conn, coords, coef)
+    m = _mesh(elem, conn.shape[0], coords.shape[0], conn, coords, coef, op)
     tu = (tuning or Tuning()).to_c()
     rc = _lib.lib().kb_integrate_lower(ctypes.byref(m), _prec(prec), ctypes.byref(tu), _ptr(out), _ptr(status),
                                        ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
@@ -437,4 +449,4 @@ __all__ = ["Builder", "BatchBuilder", "Batch", "LowerCSR", "KBuildError", "Tunin
            "build_lower_csr_batched", "assemble_lower_csr", "integrate_lower", "adjoint_lower", "lower_csr_values",
            "pack_batch", "plan", "plan_batched",
            "autotune", "default_candidates", "status_string", "version", "value_dtype", "STAGE_NAMES", "KB_N_STAGES",
-           "KB_HEX8", "KB_TET4", "KB_FP64", "KB_FP32", "KB_FP32_FB64"]
+           "KB_HEX8", "KB_TET4", "KB_FP64", "KB_FP32", "KB_FP32_FB64", "KB_OP_STIFFNESS", "KB_OP_MASS"]

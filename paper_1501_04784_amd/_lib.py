@@ -8,6 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libkbuild.so")
 
 KB_HEX8, KB_TET4 = 8, 4
+KB_OP_STIFFNESS, KB_OP_MASS = 0, 1
 KB_FP64, KB_FP32, KB_FP32_FB64 = 0, 1, 2
 KB_OK, KB_EINVAL, KB_ERANGE, KB_ENOSPC, KB_EHIP = 0, -1, -2, -3, -4
 KB_STATUS_WORDS = 4
@@ -23,7 +24,7 @@ EXPORTS = ("kb_plan", "kb_build_lower_csr", "kb_integrate_lower", "kb_assemble_l
 class KbMesh(ctypes.Structure):
     _fields_ = [
         ("elem", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("op", ctypes.c_int32),
         ("n_elem", ctypes.c_int64),
         ("n_node", ctypes.c_int64),
         ("conn", ctypes.c_void_p),

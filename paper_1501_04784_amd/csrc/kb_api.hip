@@ -33,6 +33,7 @@ int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 struct Plan {
   int nen = 0, te = 0, prec = 0, block = kDefaultBlock;
+  int op = KB_OP_STIFFNESS;            // element integrand
   float tau = kDefaultTau;
   int64_t nel = 0, nn = 0, T = 0;
   size_t vbytes = 8;
@@ -46,7 +47,7 @@ struct Plan {
   size_t lds1 = 0, lds2 = 0;
   // workspace offsets
   size_t o_coords4 = 0, o_hist = 0, o_histT = 0, o_part = 0, o_total = 0, o_bstart = 0, o_segbase = 0, o_hist2 = 0, o_seg2b = 0, o_emax = 0,
-         o_row1 = 0, o_col1 = 0, o_val1 = 0, o_key2 = 0, o_val2 = 0, o_sbb = 0, o_rowoff = 0, o_usub = 0, o_ubase = 0,
+         o_klow = 0, o_row1 = 0, o_col1 = 0, o_val1 = 0, o_key2 = 0, o_val2 = 0, o_sbb = 0, o_rowoff = 0, o_usub = 0, o_ubase = 0,
          total = 0;
 };
 
@@ -79,7 +80,8 @@ int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p) {
   if (!m) return KB_EINVAL;
   if (m->elem != KB_HEX8 && m->elem != KB_TET4) return KB_EINVAL;
   if (prec != KB_FP64 && prec != KB_FP32 && prec != KB_FP32_FB64) return KB_EINVAL;
-  if (m->n_elem < 0 || m->n_node < 0 || m->reserved != 0) return KB_EINVAL;
+  if (m->n_elem < 0 || m->n_node < 0 || (m->op != KB_OP_STIFFNESS && m->op != KB_OP_MASS)) return KB_EINVAL;
+  p->op = m->op;
   p->nen = m->elem;
   p->te = m->elem * (m->elem + 1) / 2;
   p->prec = prec;
@@ -169,6 +171,8 @@ int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p) {
   p->o_hist2 = take(4 * (size_t)(p->nseg_max * p->p2));
   p->o_seg2b = take(4 * (size_t)p->nseg_max);
   p->o_emax = take(4);
+  // mass builds integrate into element values first, then assemble them
+  p->o_klow = take(p->op == KB_OP_MASS ? p->vbytes * T : 0);
   p->o_row1 = take(2 * T);
   p->o_col1 = take(4 * T);
   p->o_val1 = take(p->vbytes * T);
@@ -391,13 +395,22 @@ int build_impl(const Plan& p, const kb_mesh* m, const void* klow, unsigned char*
     k_segments<<<1, 256, 0, s>>>(bstart, p.nb, kSeg, segbase);
     KB_LAUNCH_CHECK();
   }
-  if (p.ntiles > 0 && p.nb > 0 && !klow && p.nn > 0) {
+  if (p.ntiles > 0 && p.nb > 0 && !klow && p.op == KB_OP_STIFFNESS && p.nn > 0) {
     k_pad_coords<<<(unsigned)std::min<int64_t>(div_up(p.nn, 256), 8192), 256, 0, s>>>(m->coords, p.nn,
                                                                                      (double4*)(ws + p.o_coords4));
     KB_LAUNCH_CHECK();
   }
-  // the integrate stage is exactly one kernel (pass 1)
+  // the integrate stage is exactly one kernel (pass 1) for the stiffness matrix; a mass
+  // matrix is integrated into element values first and then assembled from them
   KB_TRY(ev.rec(KB_STAGE_INTEGRATE));
+  if (!klow && p.op == KB_OP_MASS) {
+    if (p.nel > 0) {
+      k_integrate_store<NEN, P, Op::Mass><<<grid_for(p.nel, 256), 256, 0, s>>>(
+          m->conn, m->coords, m->coef, p.nel, p.nn, p.tau, (V*)(ws + p.o_klow), status);
+      KB_LAUNCH_CHECK();
+    }
+    klow = ws + p.o_klow;
+  }
   if (p.ntiles > 0 && p.nb > 0) {
     if (klow) {
       KB_TRY((launch_pass1<NEN, P, true>(p, m, klow, ws, status, s)));
@@ -430,8 +443,13 @@ int integrate_impl(const Plan& p, const kb_mesh* m, void* vals, uint32_t* status
   KB_LAUNCH_CHECK();
   for (int i = KB_STAGE_COUNT; i <= KB_STAGE_INTEGRATE; ++i) KB_TRY(ev.rec(i));
   if (p.nel > 0) {
-    k_integrate_store<NEN, P><<<grid_for(p.nel, p.block), p.block, 0, s>>>(m->conn, m->coords, m->coef, p.nel, p.nn,
-                                                                          p.tau, (V*)vals, status);
+    const int blk = std::min(p.block, 256);  // the kernel is built for at most 256 lanes
+    if (p.op == KB_OP_MASS)
+      k_integrate_store<NEN, P, Op::Mass><<<grid_for(p.nel, blk), blk, 0, s>>>(m->conn, m->coords, m->coef, p.nel,
+                                                                              p.nn, p.tau, (V*)vals, status);
+    else
+      k_integrate_store<NEN, P><<<grid_for(p.nel, blk), blk, 0, s>>>(m->conn, m->coords, m->coef, p.nel, p.nn, p.tau,
+                                                                    (V*)vals, status);
     KB_LAUNCH_CHECK();
   }
   for (int i = KB_STAGE_HISTOGRAM; i <= KB_N_STAGES; ++i) KB_TRY(ev.rec(i));
@@ -453,7 +471,7 @@ int dispatch_integrate(const Plan& p, const kb_mesh* m, void* vals, uint32_t* st
 // the batch as one mesh (its connectivity replaced by the shifted copy at launch)
 int batch_as_mesh(const kb_batch* b, kb_mesh* m) {
   if (!b || b->n_mesh < 0) return KB_EINVAL;
-  *m = kb_mesh{b->elem, 0, b->n_elem, b->n_node, b->conn, b->coords, b->coef};
+  *m = kb_mesh{b->elem, KB_OP_STIFFNESS, b->n_elem, b->n_node, b->conn, b->coords, b->coef};
   return KB_OK;
 }
 
@@ -621,7 +639,7 @@ int kb_build_lower_csr_batched(const kb_batch* batch, int prec, const kb_tuning*
 static int adjoint_layout(const kb_mesh* m, size_t* gel, size_t* acc, size_t* emax, size_t* total) {
   if (!m) return KB_EINVAL;
   if (m->elem != KB_HEX8 && m->elem != KB_TET4) return KB_EINVAL;
-  if (m->n_elem < 0 || m->n_node < 0 || m->reserved != 0) return KB_EINVAL;
+  if (m->n_elem < 0 || m->n_node < 0 || m->op != KB_OP_STIFFNESS) return KB_EINVAL;
   if (m->n_node >= (int64_t)INT32_MAX || m->n_elem > (int64_t)INT32_MAX / m->elem) return KB_ERANGE;
   size_t off = 0;
   auto take = [&](size_t bytes) {

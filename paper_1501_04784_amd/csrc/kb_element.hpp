@@ -168,6 +168,69 @@ __device__ __forceinline__ bool tet_integrate(const GT (&X)[4][3], AT (&k)[10], 
   return det > GT(0);
 }
 
+// ---- consistent mass matrix: m_ab = integral of N_a N_b (c applied by the caller) ------
+// N_a at brick point q: (1 + r_a r)(1 + s_a s)(1 + t_a t) / 8
+__host__ __device__ constexpr double hex_N(int q, int a) {
+  return (1.0 + hex_sign(a, 0) * hex_qp(q, 0)) * (1.0 + hex_sign(a, 1) * hex_qp(q, 1)) *
+         (1.0 + hex_sign(a, 2) * hex_qp(q, 2)) / 8.0;
+}
+
+// brick: sum over the 2x2x2 points of |J_q| N_a N_b (exact for affine bricks)
+template <typename GT, typename AT, bool CHECK>
+__device__ __forceinline__ bool hex_mass(const GT (&X)[8][3], AT (&m)[36], GT tau, bool* need_fb) {
+  bool ok = true;
+#pragma unroll
+  for (int p = 0; p < 36; ++p) m[p] = AT(0);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    GT J[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        GT s = GT(0);
+#pragma unroll
+        for (int a = 1; a < 8; ++a) s += GT(hex_dN(q, i, a)) * X[a][j];
+        J[i][j] = s;
+      }
+    GT A[3][3];
+    const GT det = adjugate(J, A);
+    ok = ok && (det > GT(0));
+    if (CHECK) {
+      if (ill_conditioned(J, A, det, tau)) *need_fb = true;
+    }
+    const AT d = AT(det);
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+      for (int b = 0; b <= a; ++b) m[lidx(a, b)] += d * AT(hex_N(q, a) * hex_N(q, b));
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  return ok;
+}
+
+// tetrahedron: the exact integral of two barycentric coordinates, V (1 + delta_ab) / 20
+// with V = |J| / 6
+template <typename GT, typename AT, bool CHECK>
+__device__ __forceinline__ bool tet_mass(const GT (&X)[4][3], AT (&m)[10], GT tau, bool* need_fb) {
+  GT J[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) J[i][j] = X[i + 1][j];
+  GT A[3][3];
+  const GT det = adjugate(J, A);
+  if (CHECK) {
+    if (ill_conditioned(J, A, det, tau)) *need_fb = true;
+  }
+  const AT f = AT(det) / AT(120);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b <= a; ++b) m[lidx(a, b)] = a == b ? AT(2) * f : f;
+  return det > GT(0);
+}
+
 template <int NEN>
 struct ElemTraits;
 template <>
@@ -179,12 +242,22 @@ struct ElemTraits<4> {
   static constexpr int T = 10;
 };
 
-template <int NEN, typename GT, typename AT, bool CHECK>
+// the element integrand: stiffness (Eq. 7-9) or consistent mass
+enum class Op { Stiffness = 0, Mass = 1 };
+
+template <int NEN, typename GT, typename AT, bool CHECK, Op OP = Op::Stiffness>
 __device__ __forceinline__ bool integrate(const GT (&X)[NEN][3], AT (&k)[ElemTraits<NEN>::T], GT tau, bool* need_fb) {
-  if constexpr (NEN == 8)
-    return hex_integrate<GT, AT, CHECK>(X, k, tau, need_fb);
-  else
-    return tet_integrate<GT, AT, CHECK>(X, k, tau, need_fb);
+  if constexpr (OP == Op::Mass) {
+    if constexpr (NEN == 8)
+      return hex_mass<GT, AT, CHECK>(X, k, tau, need_fb);
+    else
+      return tet_mass<GT, AT, CHECK>(X, k, tau, need_fb);
+  } else {
+    if constexpr (NEN == 8)
+      return hex_integrate<GT, AT, CHECK>(X, k, tau, need_fb);
+    else
+      return tet_integrate<GT, AT, CHECK>(X, k, tau, need_fb);
+  }
 }
 
 }  // namespace kb

@@ -269,7 +269,7 @@ __device__ __forceinline__ void element_values_at(const double (&Xn)[NEN][3], do
 
 // Gather and integrate element e.  E must be valid.  Each node's offset from node 0 is
 // formed as soon as it arrives, so at most two nodes' FP64 coordinates are live.
-template <int NEN, Prec P, typename NODES>
+template <int NEN, Prec P, typename NODES, Op OP = Op::Stiffness>
 __device__ __forceinline__ void element_values(const NODES& nodes, const double* __restrict__ coef, int64_t e,
                                                const int32_t (&E)[NEN], float tau,
                                                typename PrecTraits<P>::V (&k)[ElemTraits<NEN>::T], uint32_t* f,
@@ -290,7 +290,7 @@ __device__ __forceinline__ void element_values(const NODES& nodes, const double*
 #pragma unroll
       for (int j = 0; j < 3; ++j) X[a][j] = xa[j] - X0[j];
     }
-    ok = integrate<NEN, double, double, false>(X, k, 0.0, nullptr);
+    ok = integrate<NEN, double, double, false, OP>(X, k, 0.0, nullptr);
   } else {
     float X[NEN][3];
     X[0][0] = X[0][1] = X[0][2] = 0.f;
@@ -302,7 +302,7 @@ __device__ __forceinline__ void element_values(const NODES& nodes, const double*
       for (int j = 0; j < 3; ++j) X[a][j] = (float)(xa[j] - X0[j]);
     }
     bool need_fb = false;
-    ok = integrate<NEN, float, float, P == Prec::F32FB>(X, k, tau, &need_fb);
+    ok = integrate<NEN, float, float, P == Prec::F32FB, OP>(X, k, tau, &need_fb);
     if constexpr (P == Prec::F32FB) {
       if (need_fb) {
         // Jacobian, determinant and adjugate in FP64 for this element (nodes re-read)
@@ -315,7 +315,7 @@ __device__ __forceinline__ void element_values(const NODES& nodes, const double*
 #pragma unroll
           for (int j = 0; j < 3; ++j) Xd[a][j] = xa[j] - X0[j];
         }
-        ok = integrate<NEN, double, float, false>(Xd, k, 0.0, nullptr);
+        ok = integrate<NEN, double, float, false, OP>(Xd, k, 0.0, nullptr);
         *fb += 1;
       }
     }
@@ -330,7 +330,7 @@ __device__ __forceinline__ void element_values(const NODES& nodes, const double*
   if (!finite) *f |= KB_F_NONFINITE;
 }
 
-template <int NEN, Prec P>
+template <int NEN, Prec P, Op OP = Op::Stiffness>
 __global__ __launch_bounds__(256) void k_integrate_store(const int32_t* __restrict__ conn,
                                                          const double* __restrict__ coords,
                                                          const double* __restrict__ coef, int64_t n_elem,
@@ -350,7 +350,7 @@ __global__ __launch_bounds__(256) void k_integrate_store(const int32_t* __restri
 #pragma unroll
     for (int p = 0; p < T; ++p) k[p] = V(0);
   } else {
-    element_values<NEN, P>(NodesXYZ{coords}, coef, e, E, tau, k, &f, &fb);
+    element_values<NEN, P, NodesXYZ, OP>(NodesXYZ{coords}, coef, e, E, tau, k, &f, &fb);
   }
 #pragma unroll
   for (int p = 0; p < T; ++p) out[e * T + p] = k[p];

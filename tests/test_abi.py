@@ -33,7 +33,7 @@ def test_header_constants_match_binding():
     consts = dict(re.findall(r"#define\s+(KB_\w+)\s+\(?(-?\d+)u?\)?", src))
     for name in ("KB_HEX8", "KB_TET4", "KB_FP64", "KB_FP32", "KB_FP32_FB64", "KB_OK", "KB_EINVAL", "KB_ERANGE",
                  "KB_ENOSPC", "KB_EHIP", "KB_STATUS_WORDS", "KB_F_INDEX", "KB_F_REPEAT", "KB_F_INVERTED",
-                 "KB_F_NONFINITE", "KB_F_CAPACITY", "KB_N_STAGES"):
+                 "KB_F_NONFINITE", "KB_F_CAPACITY", "KB_N_STAGES", "KB_OP_STIFFNESS", "KB_OP_MASS"):
         assert int(consts[name]) == getattr(_lib, name), name
 
 
@@ -192,3 +192,17 @@ def test_plan_adjoint_and_argument_errors():
         assert call(**{k: None}) == _lib.KB_EINVAL, k
     bad = KbMesh(5, 0, 100, 200, 0x1000, 0x1000, 0x1000)
     assert L.kb_plan_adjoint(ctypes.byref(bad), ctypes.byref(ws)) == _lib.KB_EINVAL
+
+
+def test_operator_field():
+    L = _lib.lib()
+    ws0, ws1 = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    m = KbMesh(4, 0, 1000, 500, None, None, None)
+    assert L.kb_plan(ctypes.byref(m), 1, None, ctypes.byref(ws0), None) == 0
+    m.op = 1  # mass: element values are integrated into the workspace first
+    assert L.kb_plan(ctypes.byref(m), 1, None, ctypes.byref(ws1), None) == 0
+    assert ws1.value >= ws0.value + 4 * 10 * 1000 - 256  # (an empty region still takes one aligned block)
+    m.op = 2
+    assert L.kb_plan(ctypes.byref(m), 1, None, ctypes.byref(ws1), None) == _lib.KB_EINVAL
+    m.op = 1  # the adjoint is for the stiffness matrix only
+    assert L.kb_plan_adjoint(ctypes.byref(m), ctypes.byref(ws1)) == _lib.KB_EINVAL
