@@ -115,6 +115,8 @@ def parse():
     ap.add_argument("--profile-steps", action="store_true", help="no stage events (for profiler runs)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
+    ap.add_argument("--op", default="stiffness", choices=["stiffness", "mass"],
+                    help="element integrand: stiffness matrix (default) or consistent mass matrix")
     ap.add_argument("--adjoint", action="store_true",
                     help="also time the adjoint (dL/dc, dL/dX of L = sum W K, seeded N(0,1) weights), FP64")
     ap.add_argument("--block", type=int, default=0, help="tuning: element tile / block size")
@@ -123,14 +125,14 @@ def parse():
     return ap.parse_args()
 
 
-def time_builds(kb, torch, mesh_dev, m, prec, steps, warmup, stage_events=True, tuning=None):
+def time_builds(kb, torch, mesh_dev, m, prec, steps, warmup, stage_events=True, tuning=None, op="stiffness"):
     if isinstance(mesh_dev, kb.Batch):
         b = kb.BatchBuilder(mesh_dev, prec=prec, tuning=tuning)
         run = lambda ev=None: b.run(stage_events=ev)  # noqa: E731
         result = lambda: b.results(check=True)  # noqa: E731
     else:
         conn, coords, coef = mesh_dev
-        b = kb.Builder(m.elem, m.n_elem, m.n_node, prec=prec, tuning=tuning)
+        b = kb.Builder(m.elem, m.n_elem, m.n_node, prec=prec, tuning=tuning, op=op)
         run = lambda ev=None: b.run(conn, coords, coef, stage_events=ev)  # noqa: E731
         result = lambda: b.result(check=True, allow_flags=0)  # noqa: E731
     stream = torch.cuda.current_stream()
@@ -260,7 +262,7 @@ def main():
 
     tuning = kb.Tuning(block=args.block, bucket_bits=args.bucket_bits, sub_bits=args.sub_bits)
     ms, wall_ms, stages, res = time_builds(kb, torch, mesh_dev, m, prec, args.steps, args.warmup,
-                                           stage_events=not args.profile_steps, tuning=tuning)
+                                           stage_events=not args.profile_steps, tuning=tuning, op=args.op)
     nnz = res.nnz
     print(f"[bench] {prec}: {ms:.3f} ms/step, nnz {nnz}, fallback elements {res.n_fallback}", file=sys.stderr,
           flush=True)
@@ -270,7 +272,8 @@ def main():
         "metric": METRIC, "value": value, "unit": "elements/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if prec == "fp64" else "f32", "data": "synthetic",
-        "config": {"workload": desc, "n_elem": m.n_elem, "n_node": m.n_node, "nnz": nnz, "precision": prec,
+        "config": {"workload": desc if args.op == "stiffness" else desc + ", consistent mass matrix",
+                   "n_elem": m.n_elem, "n_node": m.n_node, "nnz": nnz, "precision": prec,
                    "fp64_fallback_elements": res.n_fallback, "parallelism": "single GPU",
                    "tuning": {"block": args.block, "bucket_bits": args.bucket_bits, "sub_bits": args.sub_bits}},
         "path_hbm_frac": ab["path"] / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
@@ -287,7 +290,7 @@ def main():
     if not args.no_fp64 and prec != "fp64":
         ms64, _, st64, r64 = time_builds(kb, torch, mesh_dev, m, "fp64", max(3, args.steps // 2), 2,
                                          stage_events=False, tuning=kb.Tuning(bucket_bits=args.bucket_bits,
-                                                                              sub_bits=args.sub_bits))
+                                                                              sub_bits=args.sub_bits), op=args.op)
         out["fp64"] = {"ms_per_step": ms64, "value": m.n_elem / (ms64 * 1e-3)}
         out["speedup_vs_fp64"] = ms64 / ms
         print(f"[bench] fp64: {ms64:.3f} ms/step", file=sys.stderr, flush=True)

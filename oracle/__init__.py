@@ -43,6 +43,8 @@ def lib():
         L.orc_element_mass_lower.restype = i32
         L.orc_integrate_mass_lower.argtypes = [i32, i64, i64, p, p, p, p]
         L.orc_integrate_mass_lower.restype = i64
+        L.orc_assemble_lower_csr_dof.argtypes = [i32, i32, i64, i64, p, p, p, p, p, i64, p]
+        L.orc_assemble_lower_csr_dof.restype = i64
         L.orc_adjoint_lower.argtypes = [i32, i64, i64, p, p, p, p, p, p, p, p]
         L.orc_adjoint_lower.restype = i64
         _lib = L
@@ -192,3 +194,13 @@ def build_mass_mesh(mesh):
     mlow, f = integrate_mass_lower(mesh.elem, mesh.conn, mesh.coords, mesh.coef)
     rp, col, val, f2 = assemble_lower_csr(mesh.elem, mesh.conn, mesh.n_node, mlow)
     return rp, col, val, f | f2
+
+
+def assemble_lower_csr_dof(elem, dof, conn, n_node, klow):
+    """Lower CSR (dof * n_node rows) of element matrices with dof components per node."""
+    conn = _c(conn, np.int32)
+    klow = _c(klow, np.float64)
+    nd = elem * dof
+    cap = conn.shape[0] * nd * (nd + 1) // 2
+    return _csr_call(lib().orc_assemble_lower_csr_dof, dof * n_node, cap, elem, dof, conn.shape[0], n_node, _p(conn),
+                     _p(klow))

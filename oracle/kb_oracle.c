@@ -633,3 +633,42 @@ int64_t orc_integrate_mass_lower(int elem, int64_t n_elem, int64_t n_node, const
   }
   return (int64_t)flags;
 }
+
+/* ---- several degrees of freedom per node (Alg. 1, Mapping with DOFxn) -------------
+ *
+ * Element matrices of nen * dof local rows: local DOF p = a * dof + i (node a,
+ * component i) is the global DOF dof * E_a + i.  klow[e * T + p(p+1)/2 + q] holds the
+ * lower triangle (q <= p) of each element's matrix, T = (nen dof)(nen dof + 1) / 2.
+ * The global lower CSR has dof * n_node rows; pairs map to (max, min) of the two global
+ * DOFs as in the scalar case.  Returns nnz (>= 0) or -1.
+ */
+int64_t orc_assemble_lower_csr_dof(int elem, int dof, int64_t n_elem, int64_t n_node, const int32_t* conn,
+                                   const double* klow, int32_t* row_ptr, int32_t* col_idx, double* vals,
+                                   int64_t cap, uint32_t* flags_out) {
+  int nen = elem;
+  if ((elem != 8 && elem != 4) || dof < 1 || dof > 3) return -1;
+  int nd = nen * dof;
+  int64_t T = (int64_t)nd * (nd + 1) / 2;
+  trip_t* t = (trip_t*)malloc(sizeof(trip_t) * (size_t)(n_elem * T > 0 ? n_elem * T : 1));
+  if (!t) return -1;
+  int64_t nt = 0;
+  unsigned flags = 0;
+  for (int64_t e = 0; e < n_elem; ++e) {
+    const int32_t* E = conn + e * nen;
+    unsigned f = check_element(nen, E, n_node);
+    flags |= f;
+    if (f) continue;
+    for (int p = 0; p < nd; ++p)
+      for (int q = 0; q <= p; ++q) {
+        uint32_t gp = (uint32_t)(dof * E[p / dof] + p % dof), gq = (uint32_t)(dof * E[q / dof] + q % dof);
+        uint32_t row = gp > gq ? gp : gq, col = gp > gq ? gq : gp;
+        t[nt].key = ((uint64_t)row << 32) | col;
+        t[nt].val = klow[e * T + (int64_t)p * (p + 1) / 2 + q];
+        ++nt;
+      }
+  }
+  int64_t nnz = compress(t, nt, (int64_t)dof * n_node, row_ptr, col_idx, vals, cap);
+  free(t);
+  if (flags_out) *flags_out = flags;
+  return nnz;
+}
