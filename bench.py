@@ -119,6 +119,8 @@ def parse():
                     help="element integrand: stiffness matrix (default) or consistent mass matrix")
     ap.add_argument("--adjoint", action="store_true",
                     help="also time the adjoint (dL/dc, dL/dX of L = sum W K, seeded N(0,1) weights), FP64")
+    ap.add_argument("--dof", type=int, default=1, choices=[1, 2, 3],
+                    help="also time the assembly of k ⊗ I_dof element matrices (several DOFs per node)")
     ap.add_argument("--block", type=int, default=0, help="tuning: element tile / block size")
     ap.add_argument("--bucket-bits", type=int, default=0, help="tuning: log2 rows per first-level bucket")
     ap.add_argument("--sub-bits", type=int, default=0, help="tuning: log2 rows per sub-bucket")
@@ -186,6 +188,69 @@ def time_adjoint(kb, torch, mesh_dev, m, steps, warmup):
     ms = t0.elapsed_time(t1) / steps
     return {"ms_per_step": ms, "value": m.n_elem / (ms * 1e-3), "unit": "elements/s",
             "note": "includes the workspace and output allocation of each call"}
+
+
+def kron_values(torch, k1, elem, dof):
+    """Packed lower triangles of k ⊗ I_dof from packed scalar ones (input preparation)."""
+    src = []
+    for p in range(elem * dof):
+        for q in range(p + 1):
+            a, c = divmod(p, dof)
+            b, c2 = divmod(q, dof)
+            src.append(a * (a + 1) // 2 + b if c == c2 else -1)
+    src = torch.tensor(src, device=k1.device)
+    out = k1[:, src.clamp(min=0)]
+    return torch.where(src[None, :] >= 0, out, torch.zeros_like(out)).contiguous()
+
+
+def time_dof(kb, torch, mesh_dev, m, prec, dof, steps, warmup, cpu_sample):
+    """Assembly only of element matrices with ``dof`` components per node (k_e ⊗ I from the
+    mesh's own stiffness values), timed per stage like the main build."""
+    import numpy as np
+
+    import oracle
+
+    conn, coords, coef = mesh_dev
+    k1, _ = kb.integrate_lower(conn, coords, coef, m.elem, prec=prec)
+    kd = kron_values(torch, k1, m.elem, dof)
+    del k1
+    b = kb.Builder(m.elem, m.n_elem, m.n_node, prec=prec, dof=dof)
+    for _ in range(warmup):
+        b.run(conn, None, None, klow=kd)
+    res = b.result(check=True)
+    n_ev = kb.KB_N_STAGES + 1
+    evs = [kb._lib.HipEvents(n_ev) for _ in range(steps)]
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for s in range(steps):
+        b.run(conn, None, None, klow=kd, stage_events=evs[s].handles)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    stages = {name: sum(e.elapsed_ms(i, i + 1) for e in evs) / steps for i, name in enumerate(kb.STAGE_NAMES)}
+    for e in evs:
+        e.close()
+    nd = m.elem * dof
+    T = m.n_elem * nd * (nd + 1) // 2
+    out = {"dof": dof, "ms_per_step": ms, "value": m.n_elem / (ms * 1e-3), "unit": "elements/s",
+           "pairs_per_s": T / (ms * 1e-3), "n_pairs": T, "nnz": res.nnz, "rows": dof * m.n_node, "stages_ms": stages,
+           "note": "assembly only (values given), k_e ⊗ I_dof from the mesh's stiffness values"}
+    if cpu_sample:
+        n = max(1, min(m.n_elem, cpu_sample))
+        kh = kd[:n].double().cpu().numpy()
+        ch = np.ascontiguousarray(m.conn[:n])
+        oracle.lib()
+        t = time.perf_counter()
+        oracle.assemble_lower_csr_dof(m.elem, dof, ch, m.n_node, kh)
+        dt = time.perf_counter() - t
+        out["cpu_baseline"] = {"value": n / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
+                               "sample": f"first {n:,} of the {m.n_elem:,} elements, single-threaded FP64 C "
+                                         f"oracle assembly (sort + CSR), {dt:.1f} s"}
+    del kd, b
+    torch.cuda.empty_cache()
+    return out
 
 
 class BatchTotals:
@@ -297,6 +362,11 @@ def main():
     if args.adjoint and cid != 4:
         out["adjoint"] = time_adjoint(kb, torch, mesh_dev, m, args.steps, args.warmup)
         print(f"[bench] adjoint: {out['adjoint']['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+    if args.dof > 1 and cid != 4:
+        out["dof_assembly"] = time_dof(kb, torch, mesh_dev, m, prec, args.dof, args.steps, args.warmup,
+                                       0 if args.no_cpu else max(1, args.cpu_sample // (10 * args.dof * args.dof)))
+        print(f"[bench] dof {args.dof} assembly: {out['dof_assembly']['ms_per_step']:.3f} ms/step", file=sys.stderr,
+              flush=True)
     if not args.no_cpu:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(meshes if cid == 4 else m, args.cpu_sample)

@@ -131,7 +131,10 @@ typedef struct {
  * workspace needed by kb_build_lower_csr and kb_assemble_lower_csr for this mesh
  * shape and precision, and *n_triplets = n_elem * nen*(nen+1)/2, an upper bound on
  * nnz (so cap = *n_triplets always suffices).  Either output pointer may be NULL.
- * Only elem, n_elem and n_node of the mesh are read.
+ * Only elem, op, n_elem and n_node of the mesh are read.  KB_ERANGE when n_node or T
+ * exceeds int32 indexing; KB_EINVAL also when the matrix has more rows than the
+ * row buckets can hold (each pass-1 workgroup keeps two counters per bucket in LDS:
+ * about 8e7 rows, with the default tuning).
  */
 int kb_plan(const kb_mesh* mesh, int prec, const kb_tuning* tuning, size_t* ws_bytes, int64_t* n_triplets);
 
@@ -167,6 +170,29 @@ int kb_integrate_lower(const kb_mesh* mesh, int prec, const kb_tuning* tuning, v
 int kb_assemble_lower_csr(const kb_mesh* mesh, int prec, const kb_tuning* tuning, const void* klow, void* ws,
                           size_t ws_bytes, int32_t* row_ptr, int32_t* col_idx, void* vals, int64_t cap,
                           int64_t* nnz_dev, uint32_t* status_dev, void* stream);
+
+/*
+ * Several degrees of freedom per node (Alg. 1, the mapping of local to global indices
+ * with DOFs per node): element matrices of nd = nen * dof rows, local row a*dof + i
+ * standing for component i of corner a, global DOF dof * E_a + i.  K has dof * n_node
+ * rows.  Assembly only, from given values (as kb_assemble_lower_csr): the integrands of
+ * this library are scalar, vector problems bring their own element matrices.
+ *   dof       1, 2 or 3 (1 is exactly kb_assemble_lower_csr)
+ *   klow      device [n_elem][nd*(nd+1)/2], packed lower order p = r*(r+1)/2 + s, s <= r,
+ *             double for KB_FP64, float otherwise
+ *   row_ptr   device [dof * n_node + 1]; other outputs as for kb_build_lower_csr
+ * mesh->op, mesh->coords and mesh->coef are not read, nor tuning->block (the element
+ * tile follows from the pairs per element).  A node id outside [0, n_node)
+ * or repeated within an element is flagged as in kb_build_lower_csr and the element left
+ * out.  Host only: kb_plan_dof sizes the workspace (and T = n_elem * nd*(nd+1)/2).
+ * Errors: KB_EINVAL for dof outside 1..3 or a bad argument, KB_ERANGE when dof * n_node
+ * or T exceeds int32 indexing, KB_ENOSPC for a short workspace.
+ */
+int kb_plan_dof(const kb_mesh* mesh, int dof, int prec, const kb_tuning* tuning, size_t* ws_bytes,
+                int64_t* n_triplets);
+int kb_assemble_lower_csr_dof(const kb_mesh* mesh, int dof, int prec, const kb_tuning* tuning, const void* klow,
+                              void* ws, size_t ws_bytes, int32_t* row_ptr, int32_t* col_idx, void* vals, int64_t cap,
+                              int64_t* nnz_dev, uint32_t* status_dev, void* stream);
 
 /*
  * Batches.  Many independent meshes of one element type, built by one enqueued sequence

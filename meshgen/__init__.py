@@ -221,3 +221,9 @@ def counts(elem: int, nx: int, ny: int | None = None, nz: int | None = None):
     nel = cells * (1 if elem == 8 else 6)
     nen = elem
     return nel, (nx + 1) * (ny + 1) * (nz + 1), nel * nen * (nen + 1) // 2
+
+
+def element_matrices(n_elem: int, nd: int, seed: int = 6) -> np.ndarray:
+    """Seeded N(0,1) packed lower triangles [n_elem, nd(nd+1)/2] of symmetric element
+    matrices (inputs of the assembly-only paths; no physics)."""
+    return streams(seed)[5].standard_normal((n_elem, nd * (nd + 1) // 2))

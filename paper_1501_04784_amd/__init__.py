@@ -84,14 +84,21 @@ class Tuning:
         return KbTuning(int(self.block), int(self.bucket_bits), float(self.fb_tau), int(self.sub_bits), events)
 
 
-def plan(elem: int, n_elem: int, n_node: int, prec="fp64", tuning: Tuning | None = None, op="stiffness"):
-    """(workspace bytes, number of triplets) for a mesh shape."""
+def plan(elem: int, n_elem: int, n_node: int, prec="fp64", tuning: Tuning | None = None, op="stiffness",
+         dof: int = 1):
+    """(workspace bytes, number of triplets) for a mesh shape (``dof`` > 1: assembly of
+    element matrices with that many components per node)."""
     ws = ctypes.c_size_t(0)
     nt = ctypes.c_int64(0)
     m = _mesh(elem, n_elem, n_node, op=op)
     tu = (tuning or Tuning()).to_c()
-    _check(_lib.lib().kb_plan(ctypes.byref(m), _prec(prec), ctypes.byref(tu), ctypes.byref(ws), ctypes.byref(nt)),
-           "kb_plan")
+    if dof == 1:
+        rc = _lib.lib().kb_plan(ctypes.byref(m), _prec(prec), ctypes.byref(tu), ctypes.byref(ws), ctypes.byref(nt))
+        _check(rc, "kb_plan")
+    else:
+        rc = _lib.lib().kb_plan_dof(ctypes.byref(m), int(dof), _prec(prec), ctypes.byref(tu), ctypes.byref(ws),
+                                    ctypes.byref(nt))
+        _check(rc, "kb_plan_dof")
     return int(ws.value), int(nt.value)
 
 
@@ -149,16 +156,17 @@ class Builder:
     """
 
     def __init__(self, elem: int, n_elem: int, n_node: int, prec="fp32fb64", tuning: Tuning | None = None,
-                 device="cuda", cap: int | None = None, op="stiffness"):
+                 device="cuda", cap: int | None = None, op="stiffness", dof: int = 1):
         self.elem, self.n_elem, self.n_node = int(elem), int(n_elem), int(n_node)
         self.prec = _prec(prec)
         self.op = _op(op)
+        self.dof = int(dof)
         self.tuning = tuning or Tuning()
-        self.ws_bytes, self.n_triplets = plan(elem, n_elem, n_node, self.prec, self.tuning, self.op)
+        self.ws_bytes, self.n_triplets = plan(elem, n_elem, n_node, self.prec, self.tuning, self.op, self.dof)
         self.cap = self.n_triplets if cap is None else int(cap)
         dev = torch.device(device)
         self.ws = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=dev)
-        self.row_ptr = torch.empty(self.n_node + 1, dtype=torch.int32, device=dev)
+        self.row_ptr = torch.empty(self.dof * self.n_node + 1, dtype=torch.int32, device=dev)
         self.col_idx = torch.empty(max(self.cap, 1), dtype=torch.int32, device=dev)
         self.vals = torch.empty(max(self.cap, 1), dtype=value_dtype(self.prec), device=dev)
         self.nnz_dev = torch.zeros(1, dtype=torch.int64, device=dev)
@@ -175,7 +183,15 @@ class Builder:
         tu = self.tuning.to_c(ev)
         m = _mesh(self.elem, self.n_elem, self.n_node, conn, coords, coef, self.op)
         L = _lib.lib()
-        if klow is None:
+        if self.dof != 1:
+            if klow is None:
+                raise ValueError("several DOFs per node: element values klow are required")
+            rc = L.kb_assemble_lower_csr_dof(ctypes.byref(m), self.dof, self.prec, ctypes.byref(tu), _ptr(klow),
+                                             _ptr(self.ws), self.ws_bytes, _ptr(self.row_ptr), _ptr(self.col_idx),
+                                             _ptr(self.vals), self.cap, _ptr(self.nnz_dev), _ptr(self.status),
+                                             ctypes.c_void_p(s.cuda_stream))
+            _check(rc, "kb_assemble_lower_csr_dof")
+        elif klow is None:
             rc = L.kb_build_lower_csr(ctypes.byref(m), self.prec, ctypes.byref(tu), _ptr(self.ws), self.ws_bytes,
                                       _ptr(self.row_ptr), _ptr(self.col_idx), _ptr(self.vals), self.cap,
                                       _ptr(self.nnz_dev), _ptr(self.status), ctypes.c_void_p(s.cuda_stream))
@@ -210,13 +226,16 @@ def build_lower_csr(conn, coords, coef, elem: int, prec="fp32fb64", tuning: Tuni
 
 
 def assemble_lower_csr(conn, n_node: int, klow, elem: int, prec="fp64", tuning: Tuning | None = None, check=True,
-                       allow_flags: int = 0, cap: int | None = None) -> LowerCSR:
-    """Assemble lower CSR K from given per-element lower values klow [n_elem, nen(nen+1)/2]."""
+                       allow_flags: int = 0, cap: int | None = None, dof: int = 1) -> LowerCSR:
+    """Assemble lower CSR K from given per-element lower values klow [n_elem, nd(nd+1)/2],
+    nd = elem * dof (local row a * dof + i is component i of corner a; K has dof * n_node
+    rows)."""
     _validate_mesh(conn, None, None, elem, need_geometry=False)
-    te = elem * (elem + 1) // 2
+    nd = elem * int(dof)
+    te = nd * (nd + 1) // 2
     if klow.dtype != value_dtype(prec) or klow.shape != (conn.shape[0], te) or not klow.is_contiguous():
         raise ValueError(f"klow must be a contiguous {value_dtype(prec)} [n_elem, {te}] tensor")
-    b = Builder(elem, conn.shape[0], n_node, prec, tuning, device=conn.device, cap=cap)
+    b = Builder(elem, conn.shape[0], n_node, prec, tuning, device=conn.device, cap=cap, dof=dof)
     b.run(conn, None, None, klow=klow)
     return b.result(check=check, allow_flags=allow_flags)
 

@@ -17,8 +17,9 @@ KB_N_STAGES = 8
 STAGE_NAMES = ("init", "count", "offsets", "integrate", "histogram", "partition", "reduce", "compress")
 
 # every function declared in include/kbuild.h
-EXPORTS = ("kb_plan", "kb_build_lower_csr", "kb_integrate_lower", "kb_assemble_lower_csr", "kb_plan_batched",
-           "kb_build_lower_csr_batched", "kb_plan_adjoint", "kb_adjoint_lower", "kb_status_string", "kb_version")
+EXPORTS = ("kb_plan", "kb_build_lower_csr", "kb_integrate_lower", "kb_assemble_lower_csr", "kb_plan_dof",
+           "kb_assemble_lower_csr_dof", "kb_plan_batched", "kb_build_lower_csr_batched", "kb_plan_adjoint",
+           "kb_adjoint_lower", "kb_status_string", "kb_version")
 
 
 class KbMesh(ctypes.Structure):
@@ -79,6 +80,10 @@ def lib():
         L.kb_integrate_lower.restype = i32
         L.kb_assemble_lower_csr.argtypes = [PM, i32, PT, p, p, sz, p, p, p, i64, p, p, p]
         L.kb_assemble_lower_csr.restype = i32
+        L.kb_plan_dof.argtypes = [PM, i32, i32, PT, ctypes.POINTER(sz), ctypes.POINTER(i64)]
+        L.kb_plan_dof.restype = i32
+        L.kb_assemble_lower_csr_dof.argtypes = [PM, i32, i32, PT, p, p, sz, p, p, p, i64, p, p, p]
+        L.kb_assemble_lower_csr_dof.restype = i32
         PB = ctypes.POINTER(KbBatch)
         L.kb_plan_batched.argtypes = [PB, i32, PT, ctypes.POINTER(sz), ctypes.POINTER(i64)]
         L.kb_plan_batched.restype = i32

@@ -27,6 +27,7 @@ constexpr int kSegThreads = 512;   // threads per pass-2 scatter workgroup
 constexpr int kTargetBuckets = 512;  // first-level buckets (pass-1 run length)
 constexpr double kSubEntries = 300;   // target distinct entries per sub-bucket
 constexpr int kHTMin = 512, kHTMax = 4096;
+constexpr size_t kWideStage = 112640;  // staged pair bytes per pass-1 tile, elements of > 8 rows
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -34,6 +35,7 @@ int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
 struct Plan {
   int nen = 0, te = 0, prec = 0, block = kDefaultBlock;
   int op = KB_OP_STIFFNESS;            // element integrand
+  int dof = 1;                         // degrees of freedom per node (assembly only)
   float tau = kDefaultTau;
   int64_t nel = 0, nn = 0, T = 0;
   size_t vbytes = 8;
@@ -47,7 +49,7 @@ struct Plan {
   size_t lds1 = 0, lds2 = 0;
   // workspace offsets
   size_t o_coords4 = 0, o_hist = 0, o_histT = 0, o_part = 0, o_total = 0, o_bstart = 0, o_segbase = 0, o_hist2 = 0, o_seg2b = 0, o_emax = 0,
-         o_klow = 0, o_row1 = 0, o_col1 = 0, o_val1 = 0, o_key2 = 0, o_val2 = 0, o_sbb = 0, o_rowoff = 0, o_usub = 0, o_ubase = 0,
+         o_klow = 0, o_dconn = 0, o_row1 = 0, o_col1 = 0, o_val1 = 0, o_key2 = 0, o_val2 = 0, o_sbb = 0, o_rowoff = 0, o_usub = 0, o_ubase = 0,
          total = 0;
 };
 
@@ -76,17 +78,22 @@ int ilog2_ceil(int64_t x) {
   return k;
 }
 
-int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p) {
+// dof > 1: element matrices with dof components per node are assembled as elements of
+// nen * dof "nodes" (global DOF dof * E_a + i); nen and nn below are those of that view
+int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p, int dof = 1) {
   if (!m) return KB_EINVAL;
   if (m->elem != KB_HEX8 && m->elem != KB_TET4) return KB_EINVAL;
   if (prec != KB_FP64 && prec != KB_FP32 && prec != KB_FP32_FB64) return KB_EINVAL;
   if (m->n_elem < 0 || m->n_node < 0 || (m->op != KB_OP_STIFFNESS && m->op != KB_OP_MASS)) return KB_EINVAL;
+  if (dof < 1 || dof > 3) return KB_EINVAL;
   p->op = m->op;
-  p->nen = m->elem;
-  p->te = m->elem * (m->elem + 1) / 2;
+  p->dof = dof;
+  p->nen = m->elem * dof;
+  p->te = p->nen * (p->nen + 1) / 2;
   p->prec = prec;
   p->nel = m->n_elem;
-  p->nn = m->n_node;
+  if (m->n_node >= (int64_t)INT32_MAX / dof) return KB_ERANGE;
+  p->nn = m->n_node * dof;
   if (p->nn >= (int64_t)INT32_MAX) return KB_ERANGE;
   if (p->nel > (int64_t)INT32_MAX / p->te) return KB_ERANGE;
   p->T = p->nel * p->te;
@@ -112,7 +119,7 @@ int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p) {
   p->colbits = 1;
   while (((int64_t)1 << p->colbits) < p->nn) ++p->colbits;
   const double avg = p->nn > 0 ? (double)p->T / (double)p->nn : 1.0;
-  const double u_row = std::max(1.0, avg / (p->nen == 4 ? 7.4 : 2.5));
+  const double u_row = std::max(1.0, avg / (m->elem == KB_TET4 ? 7.4 : 2.5));
   const int s2_max = std::min(8, 31 - p->colbits);
   if (sub_bits) {
     if (sub_bits > s2_max) return KB_EINVAL;
@@ -138,18 +145,24 @@ int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p) {
   p->p2 = 1 << (p->s1 - p->s2);
   p->nb = (int)div_up(p->nn, (int64_t)1 << p->s1);
   p->nsub = (int64_t)p->nb * p->p2;
-  // pass-1 tiles: one element per lane, pairs staged in LDS as (8-byte key, value);
-  // `block` may pick the half-size tile (two workgroups per CU)
-  {
+  // pass-1 tiles: pairs staged in LDS as (8-byte key, value).  Up to 8 rows: one
+  // element per lane, `block` may pick the half-size tile (two workgroups per CU);
+  // more rows (several DOFs per node): as many elements as keep the staged pairs near
+  // 110 KB, on 256 threads
+  if (p->nen <= 8) {
     const int big = p->nen == 4 ? (prec == KB_FP64 ? 768 : 1024) : (prec == KB_FP64 ? 192 : 256);
     const int small = big / 2 % 64 == 0 ? big / 2 : 64 * ((big / 2 + 63) / 64);
     p->tile = big;
     if (tu && (tu->block == big || tu->block == small)) p->tile = tu->block;
+    p->lds1 = (size_t)p->tile * p->te * (8 + p->vbytes) + 2 * 4 * (size_t)p->nb + 4 * (p->tile / 64 + 2);
+  } else {
+    p->tile = (int)std::min<size_t>(256, std::max<size_t>(1, kWideStage / ((size_t)p->te * (8 + p->vbytes))));
+    p->lds1 = (size_t)p->tile * p->te * (8 + p->vbytes) + 2 * 4 * (size_t)p->nb + 4 * (256 / 64 + 2) +
+              (size_t)p->tile * p->nen * 12 + 4 * (size_t)p->tile + 2 * (size_t)p->te;
   }
   p->ntiles = div_up(p->nel, p->tile);
   p->nhist = (int64_t)p->nb * p->ntiles;
   p->nseg_max = div_up(p->T, kSeg) + p->nb;
-  p->lds1 = (size_t)p->tile * p->te * (8 + p->vbytes) + 2 * 4 * (size_t)p->nb + 4 * (p->tile / 64 + 2);
   p->lds2 = (size_t)kSeg * (p->vbytes + 4 + 2) + 2 * 4 * (size_t)p->p2 + 4 * (kSegThreads / 64 + 1);
   if (p->lds1 > 163840 || p->lds2 > 163840) return KB_EINVAL;
   size_t off = 0;
@@ -160,7 +173,7 @@ int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p) {
   };
   const size_t T = (size_t)p->T;
   const int64_t scan_n = std::max(p->nhist, p->nsub + 1);
-  p->o_coords4 = take(32 * (size_t)p->nn);
+  p->o_coords4 = take(p->dof > 1 ? 0 : 32 * (size_t)p->nn);  // assembly with several DOFs: no geometry
   // scan outputs hold n + 1 words: the scan writes its total after the last entry
   p->o_hist = take(4 * (size_t)p->nhist);
   p->o_histT = take(4 * ((size_t)p->nhist + 1));
@@ -172,7 +185,8 @@ int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p) {
   p->o_seg2b = take(4 * (size_t)p->nseg_max);
   p->o_emax = take(4);
   // mass builds integrate into element values first, then assemble them
-  p->o_klow = take(p->op == KB_OP_MASS ? p->vbytes * T : 0);
+  p->o_klow = take(p->op == KB_OP_MASS && p->dof == 1 ? p->vbytes * T : 0);
+  p->o_dconn = take(p->dof > 1 ? 4 * (size_t)p->nen * (size_t)p->nel : 0);  // expanded connectivity
   p->o_row1 = take(2 * T);
   p->o_col1 = take(4 * T);
   p->o_val1 = take(p->vbytes * T);
@@ -272,14 +286,33 @@ struct TileSizes {
   static constexpr int small = big / 2 >= 64 && (big / 2) % 64 == 0 ? big / 2 : 64 * ((big / 2 + 63) / 64);
 };
 
+// elements of more than 8 rows: `tile` elements on 256 threads, one tile per workgroup
+template <int NEN, typename V>
+int launch_pass1_wide(const Plan& p, const kb_mesh* m, const void* klow, unsigned char* ws, uint32_t* status,
+                      hipStream_t s) {
+  auto kern = k_pass1_wide<NEN, V>;
+  if (!set_lds(kern, p.lds1)) return KB_EHIP;
+  kern<<<(unsigned)p.ntiles, 256, p.lds1, s>>>(m->conn, (const V*)klow, p.nel, p.nn, p.tile, p.s1, p.nb,
+                                              (const uint32_t*)(ws + p.o_hist), (uint16_t*)(ws + p.o_row1),
+                                              (uint32_t*)(ws + p.o_col1), (V*)(ws + p.o_val1),
+                                              (uint32_t*)(ws + p.o_emax), status);
+  KB_LAUNCH_CHECK();
+  return KB_OK;
+}
+
 template <int NEN, Prec P, bool FROM_VALUES>
 int launch_pass1(const Plan& p, const kb_mesh* m, const void* klow, unsigned char* ws, uint32_t* status,
                  hipStream_t s) {
-  if (p.tile == TileSizes<NEN, P>::big)
-    return launch_pass1_block<NEN, P, FROM_VALUES, TileSizes<NEN, P>::big>(p, m, klow, ws, status, s);
-  if (p.tile == TileSizes<NEN, P>::small)
-    return launch_pass1_block<NEN, P, FROM_VALUES, TileSizes<NEN, P>::small>(p, m, klow, ws, status, s);
-  return KB_EINVAL;
+  if constexpr (NEN > 8) {
+    static_assert(FROM_VALUES, "elements of more than 8 rows are assembled from given values");
+    return launch_pass1_wide<NEN, typename PrecTraits<P>::V>(p, m, klow, ws, status, s);
+  } else {
+    if (p.tile == TileSizes<NEN, P>::big)
+      return launch_pass1_block<NEN, P, FROM_VALUES, TileSizes<NEN, P>::big>(p, m, klow, ws, status, s);
+    if (p.tile == TileSizes<NEN, P>::small)
+      return launch_pass1_block<NEN, P, FROM_VALUES, TileSizes<NEN, P>::small>(p, m, klow, ws, status, s);
+    return KB_EINVAL;
+  }
 }
 
 template <typename V>
@@ -403,19 +436,23 @@ int build_impl(const Plan& p, const kb_mesh* m, const void* klow, unsigned char*
   // the integrate stage is exactly one kernel (pass 1) for the stiffness matrix; a mass
   // matrix is integrated into element values first and then assembled from them
   KB_TRY(ev.rec(KB_STAGE_INTEGRATE));
-  if (!klow && p.op == KB_OP_MASS) {
-    if (p.nel > 0) {
-      k_integrate_store<NEN, P, Op::Mass><<<grid_for(p.nel, 256), 256, 0, s>>>(
-          m->conn, m->coords, m->coef, p.nel, p.nn, p.tau, (V*)(ws + p.o_klow), status);
-      KB_LAUNCH_CHECK();
+  if constexpr (NEN <= 8) {
+    if (!klow && p.op == KB_OP_MASS) {
+      if (p.nel > 0) {
+        k_integrate_store<NEN, P, Op::Mass><<<grid_for(p.nel, 256), 256, 0, s>>>(
+            m->conn, m->coords, m->coef, p.nel, p.nn, p.tau, (V*)(ws + p.o_klow), status);
+        KB_LAUNCH_CHECK();
+      }
+      klow = ws + p.o_klow;
     }
-    klow = ws + p.o_klow;
   }
   if (p.ntiles > 0 && p.nb > 0) {
     if (klow) {
       KB_TRY((launch_pass1<NEN, P, true>(p, m, klow, ws, status, s)));
-    } else {
+    } else if constexpr (NEN <= 8) {
       KB_TRY((launch_pass1<NEN, P, false>(p, m, nullptr, ws, status, s)));
+    } else {
+      return KB_EINVAL;  // several DOFs per node: values are always given
     }
   }
   return assemble_tail<V>(p, ws, row_ptr, col_idx, (V*)vals, cap, nnz_dev, status, ev, s);
@@ -569,6 +606,60 @@ int kb_assemble_lower_csr(const kb_mesh* mesh, int prec, const kb_tuning* tuning
   static const double kEmpty = 0.0;
   return build_common(mesh, prec, tuning, klow ? klow : (const void*)&kEmpty, ws, ws_bytes, row_ptr, col_idx, vals,
                       cap, nnz_dev, status_dev, stream);
+}
+
+int kb_plan_dof(const kb_mesh* mesh, int dof, int prec, const kb_tuning* tuning, size_t* ws_bytes,
+                int64_t* n_triplets) {
+  Plan p;
+  KB_TRY(make_plan(mesh, prec, tuning, &p, dof));
+  if (ws_bytes) *ws_bytes = p.total;
+  if (n_triplets) *n_triplets = p.T;
+  return KB_OK;
+}
+
+int kb_assemble_lower_csr_dof(const kb_mesh* mesh, int dof, int prec, const kb_tuning* tuning, const void* klow,
+                              void* ws, size_t ws_bytes, int32_t* row_ptr, int32_t* col_idx, void* vals, int64_t cap,
+                              int64_t* nnz_dev, uint32_t* status_dev, void* stream) {
+  if (dof == 1)
+    return kb_assemble_lower_csr(mesh, prec, tuning, klow, ws, ws_bytes, row_ptr, col_idx, vals, cap, nnz_dev,
+                                 status_dev, stream);
+  Plan p;
+  KB_TRY(make_plan(mesh, prec, tuning, &p, dof));
+  KB_TRY(check_mesh_ptrs(mesh, false));
+  if (p.nel > 0 && !klow) return KB_EINVAL;
+  if (!row_ptr || !nnz_dev || !status_dev || cap < 0) return KB_EINVAL;
+  if (cap > 0 && (!col_idx || !vals)) return KB_EINVAL;
+  if (ws_bytes < p.total) return KB_ENOSPC;
+  if (!ws) return KB_EINVAL;
+  KB_TRY(device_cus(&p.cus));
+  auto* w = (unsigned char*)ws;
+  auto s = (hipStream_t)stream;
+  // the DOF view: elements of nen * dof rows over dof * n_node global DOFs
+  kb_mesh vm = *mesh;
+  vm.elem = p.nen;
+  vm.n_node = p.nn;
+  vm.conn = (const int32_t*)(w + p.o_dconn);
+  if (p.nel > 0) {
+    const int64_t n = p.nel * mesh->elem;
+    k_dof_conn<<<(unsigned)std::min<int64_t>(div_up(n, 256), 65536), 256, 0, s>>>(mesh->conn, n, dof,
+                                                                                   (int32_t*)(w + p.o_dconn));
+    KB_LAUNCH_CHECK();
+  }
+  static const double kEmpty = 0.0;
+  const void* kl = klow ? klow : (const void*)&kEmpty;  // selects the assembly-only path
+  Events ev{tuning ? tuning->stage_events : nullptr, s};
+  switch (p.nen) {
+    case 8:  // tetrahedra, 2 DOFs
+      return dispatch_build<8>(p, &vm, kl, w, row_ptr, col_idx, vals, cap, nnz_dev, status_dev, ev, s);
+    case 12:
+      return dispatch_build<12>(p, &vm, kl, w, row_ptr, col_idx, vals, cap, nnz_dev, status_dev, ev, s);
+    case 16:
+      return dispatch_build<16>(p, &vm, kl, w, row_ptr, col_idx, vals, cap, nnz_dev, status_dev, ev, s);
+    case 24:
+      return dispatch_build<24>(p, &vm, kl, w, row_ptr, col_idx, vals, cap, nnz_dev, status_dev, ev, s);
+    default:
+      return KB_EINVAL;
+  }
 }
 
 int kb_plan_batched(const kb_batch* batch, int prec, const kb_tuning* tuning, size_t* ws_bytes,

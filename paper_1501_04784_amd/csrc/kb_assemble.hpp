@@ -180,25 +180,34 @@ __device__ __forceinline__ void join48(uint64_t s0, int64_t s1, uint64_t& lo, ui
   hi = a_hi + (lo < s0 ? 1ull : 0ull);
 }
 
-// exact 128-bit value -> double, correctly rounded; then scaled by 2^-F
-__device__ __forceinline__ double from_fixed(uint64_t lo, uint64_t hi, int F) {
+// exact 128-bit value -> V (double or float), rounded once to nearest; then scaled by
+// 2^-F (exact unless the result is subnormal).  The 64 leading bits carry a sticky bit
+// for the rest, so the one rounding of the 64-bit integer to V is that of the whole.
+template <typename V>
+__device__ __forceinline__ V from_fixed_as(uint64_t lo, uint64_t hi, int F) {
   const bool neg = (int64_t)hi < 0;
   if (neg) {
     lo = ~lo + 1;
     hi = ~hi + (lo == 0 ? 1ull : 0ull);
   }
-  double d;
-  if (hi == 0) {
-    d = (double)lo;
-  } else {
+  uint64_t top = lo;
+  int sh = 0;
+  if (hi != 0) {
     const int lz = __clzll((long long)hi);
-    uint64_t top = lz ? ((hi << lz) | (lo >> (64 - lz))) : hi;
+    top = lz ? ((hi << lz) | (lo >> (64 - lz))) : hi;
     const uint64_t rest = lz ? (lo << lz) : lo;
-    top |= rest ? 1ull : 0ull;  // sticky bit: 64 > 53 + 2, so rounding stays correct
-    d = ldexp((double)top, 64 - lz);
+    top |= rest ? 1ull : 0ull;  // sticky bit: 64 > 53 + 2 bits, so the rounding stays correct
+    sh = 64 - lz;
   }
-  d = ldexp(d, -F);
+  V d;
+  if constexpr (sizeof(V) == 8)
+    d = ldexp(ldexp((double)top, sh), -F);
+  else
+    d = ldexpf(ldexpf((float)top, sh), -F);
   return neg ? -d : d;
+}
+__device__ __forceinline__ double from_fixed(uint64_t lo, uint64_t hi, int F) {
+  return from_fixed_as<double>(lo, hi, F);
 }
 
 // ---------------------------------------------------------------------- histogram
@@ -509,6 +518,94 @@ __global__ __launch_bounds__(BLOCK) void k_pass1_tet(const int32_t* __restrict__
   if (threadIdx.x == 0 && *sm.emax) atomicMax(emax, *sm.emax);
 }
 
+// Elements of more than eight rows (nodes with several degrees of freedom), values
+// given (assembly only).  A tile is `te` elements, few enough that their pairs fit in
+// LDS; 256 threads work on it:
+//   - per (element, row a): the row's rank r_a among the element's ids, and its run of
+//     r_a + 1 places in the tile's part of bucket E_a >> s1 (LDS counters);
+//   - per pair, one thread each, values read in storage order (coalesced): pair (p, q)
+//     belongs to the row of the larger id (a) and takes place rank(b) of that row's
+//     run, b being the other corner (the diagonal takes the last place, r_a);
+//   - the staged pairs, grouped by bucket, are written as runs (as for 4 and 8 rows).
+template <int NEN, typename V>
+__global__ __launch_bounds__(256) void k_pass1_wide(const int32_t* __restrict__ conn, const V* __restrict__ klow,
+                                                  int64_t n_elem, int64_t n_node, int te, int s1, int nb,
+                                                  const uint32_t* __restrict__ off1, uint16_t* __restrict__ orow,
+                                                  uint32_t* __restrict__ ocol, V* __restrict__ oval,
+                                                  uint32_t* __restrict__ emax, uint32_t* __restrict__ status) {
+  constexpr int T = ElemTraits<NEN>::T, NT = 256;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const Pass1Smem<V, NT> sm(smem, te * T, nb);
+  int32_t* s_E = (int32_t*)(sm.emax + 1);    // [te * NEN] the tile's connectivity
+  uint32_t* s_q = (uint32_t*)(s_E + te * NEN);  // [te * NEN] run offset of each row in its bucket
+  uint32_t* s_rank = s_q + te * NEN;            // [te * NEN] rank of each corner's id
+  uint32_t* s_ok = s_rank + te * NEN;           // [te] element valid
+  uint16_t* s_pq = (uint16_t*)(s_ok + te);      // [T] packed index -> (p << 8 | q)
+  const int64_t t = xcd_item(blockIdx.x, gridDim.x);
+  const int64_t e0 = t * te;
+  const int ne = (int)(n_elem - e0 < te ? n_elem - e0 : te);
+  for (int b = threadIdx.x; b < nb; b += NT) {
+    sm.cnt[b] = 0;
+    sm.base[b] = off1[t * nb + b];
+  }
+  if (threadIdx.x == 0) *sm.emax = 0;
+  for (int i = threadIdx.x; i < T; i += NT) {
+    int p = 0;
+    while ((p + 1) * (p + 2) / 2 <= i) ++p;
+    s_pq[i] = (uint16_t)(p << 8 | (i - p * (p + 1) / 2));
+  }
+  for (int i = threadIdx.x; i < ne * NEN; i += NT) s_E[i] = conn[e0 * NEN + i];
+  __syncthreads();
+  uint32_t flags = 0;
+  for (int el = threadIdx.x; el < ne; el += NT) {
+    int32_t E[NEN];
+#pragma unroll
+    for (int a = 0; a < NEN; ++a) E[a] = s_E[el * NEN + a];
+    const uint32_t f = check_conn<NEN>(E, n_node);
+    flags |= f;
+    s_ok[el] = f == 0;
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < ne * NEN; j += NT) {
+    const int el = j / NEN;
+    if (!s_ok[el]) continue;
+    const int32_t Ea = s_E[j];
+    uint32_t r = 0;
+#pragma unroll
+    for (int b = 0; b < NEN; ++b) r += (s_E[el * NEN + b] < Ea) ? 1u : 0u;
+    s_rank[j] = r;
+    s_q[j] = atomicAdd(&sm.cnt[Ea >> s1], r + 1);
+  }
+  __syncthreads();
+  const uint32_t n_items = block_scan_array(sm.cnt, nb, sm.scan);  // cnt: local run starts
+  uint32_t em = 0;
+  bool finite = true;
+  const V* __restrict__ k = klow + e0 * T;
+  for (int i = threadIdx.x; i < ne * T; i += NT) {
+    const int el = i / T, kk = i - el * T;
+    if (!s_ok[el]) continue;
+    const uint32_t pq = s_pq[kk];
+    const int p = (int)(pq >> 8), q = (int)(pq & 255u);
+    const int32_t Ep = s_E[el * NEN + p], Eq = s_E[el * NEN + q];
+    const bool up = Ep >= Eq;
+    const int a = up ? p : q, b = up ? q : p;
+    const int32_t Ea = up ? Ep : Eq, Eb = up ? Eq : Ep;
+    const uint32_t pos = sm.cnt[Ea >> s1] + s_q[el * NEN + a] + s_rank[el * NEN + b];
+    const V v = k[i];
+    finite = finite && isfinite((double)v);
+    const uint32_t ep = (uint32_t)biased_exponent((double)v);
+    em = (ep > em && ep < 0x7FF) ? ep : em;
+    sm.key[pos] = (uint64_t)(uint32_t)Ea << 32 | (uint32_t)Eb;
+    sm.val[pos] = v;
+  }
+  if (!finite) flags |= KB_F_NONFINITE;
+  if (flags) raise_flag(status, flags);
+  if (em) atomicMax(sm.emax, em);
+  __syncthreads();
+  if (threadIdx.x == 0 && *sm.emax) atomicMax(emax, *sm.emax);
+  pass1_write(sm, n_items, s1, NT, orow, ocol, oval);
+}
+
 // ------------------------------------------------------------------------ pass 2
 // A bucket's pairs are cut into segments of SEG; segment ids run over all buckets
 // (segbase[b] is the first segment of bucket b, segbase[nb] their number).
@@ -700,7 +797,7 @@ __device__ void pass3_global(uint32_t* key, V* val, int64_t n, int64_t r0, int R
       ++q;
     }
     tcol[u] = (int32_t)(k0 & cmask);
-    tval[u] = (V)from_fixed(lo, hi, F);
+    tval[u] = from_fixed_as<V>(lo, hi, F);
     rowoff[r0 + (k0 >> colbits)] += 1;
     ++u;
   }
@@ -851,7 +948,7 @@ __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* _
     tcol[beg + pos] = (int32_t)col;
     uint64_t lo, hi;
     join48(s_lo[h], (int64_t)s_hi[h], lo, hi);
-    tval[beg + pos] = (V)from_fixed(lo, hi, F);
+    tval[beg + pos] = from_fixed_as<V>(lo, hi, F);
   }
   for (int r = threadIdx.x; r < R; r += NT) rowoff[r0 + r] = s_ro[r];
   if (threadIdx.x == 0) usub[g] = U;

@@ -231,15 +231,11 @@ __device__ __forceinline__ bool tet_mass(const GT (&X)[4][3], AT (&m)[10], GT ta
   return det > GT(0);
 }
 
+// packed lower-triangle entries of an element matrix of NEN rows (NEN = nodes times
+// degrees of freedom per node)
 template <int NEN>
-struct ElemTraits;
-template <>
-struct ElemTraits<8> {
-  static constexpr int T = 36;
-};
-template <>
-struct ElemTraits<4> {
-  static constexpr int T = 10;
+struct ElemTraits {
+  static constexpr int T = NEN * (NEN + 1) / 2;
 };
 
 // the element integrand: stiffness (Eq. 7-9) or consistent mass

@@ -60,6 +60,23 @@ __device__ __forceinline__ void node_ranks(const int32_t (&E)[NEN], int (&r)[NEN
   }
 }
 
+// ---------------------------------------------------------------- several DOFs
+// Connectivity of the DOF view of a mesh with dof components per node: entry a*dof+i
+// of element e is the global DOF dof*E[a]+i.  An id outside [0, n_node) maps to ids
+// outside [0, dof*n_node) (a negative one stays negative; distinct ids stay distinct
+// below 2^31/dof in magnitude), so the pipeline flags the element as the node ids would.
+__global__ __launch_bounds__(256) void k_dof_conn(const int32_t* __restrict__ conn, int64_t n, int dof,
+                                                  int32_t* __restrict__ dconn) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t v = conn[t];
+    for (int i = 0; i < dof; ++i) {
+      int64_t w = dof * v + i;
+      w = w > INT32_MAX ? INT32_MAX : (w < INT32_MIN ? INT32_MIN : w);
+      dconn[t * dof + i] = (int32_t)w;
+    }
+  }
+}
+
 // ------------------------------------------------------------------------- fill
 __global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)

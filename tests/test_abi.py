@@ -206,3 +206,54 @@ def test_operator_field():
     assert L.kb_plan(ctypes.byref(m), 1, None, ctypes.byref(ws1), None) == _lib.KB_EINVAL
     m.op = 1  # the adjoint is for the stiffness matrix only
     assert L.kb_plan_adjoint(ctypes.byref(m), ctypes.byref(ws1)) == _lib.KB_EINVAL
+
+
+def _plan_dof(elem, nel, nn, dof, prec=0):
+    m = KbMesh(elem, 0, nel, nn, None, None, None)
+    ws, nt = ctypes.c_size_t(0), ctypes.c_int64(0)
+    rc = _lib.lib().kb_plan_dof(ctypes.byref(m), dof, prec, None, ctypes.byref(ws), ctypes.byref(nt))
+    return rc, ws.value, nt.value
+
+
+@pytest.mark.parametrize("elem", [8, 4])
+def test_plan_dof(elem):
+    # dof 1 is the scalar plan
+    assert _plan_dof(elem, 1000, 900, 1) == _plan(elem, 1000, 900)
+    for dof in (2, 3):
+        nd = elem * dof
+        rc, ws, nt = _plan_dof(elem, 1000, 900, dof)
+        assert rc == 0 and nt == 1000 * nd * (nd + 1) // 2
+        # at least: expanded connectivity, pass-1 and pass-2 streams, dof * n_node row offsets
+        assert ws >= 4 * nd * 1000 + (2 + 4 + 8 + 4 + 8) * nt + 4 * dof * 900
+    for dof in (0, 4, -1):
+        assert _plan_dof(elem, 10, 10, dof)[0] == _lib.KB_EINVAL
+    # dof * n_node must stay below 2^31
+    assert _plan_dof(elem, 10, (1 << 31) // 3, 3)[0] == _lib.KB_ERANGE
+    assert _plan_dof(elem, 10, (1 << 25) - 1, 2)[0] == 0  # 2^26 rows
+    # triplets of int32 indexing
+    nd = elem * 3
+    assert _plan_dof(elem, (1 << 31) // (nd * (nd + 1) // 2) + 1, 100, 3)[0] == _lib.KB_ERANGE
+
+
+def test_assemble_dof_argument_errors():
+    L = _lib.lib()
+    m = KbMesh(8, 0, 100, 200, 0x1000, None, None)
+    ws, nt = ctypes.c_size_t(0), ctypes.c_int64(0)
+    assert L.kb_plan_dof(ctypes.byref(m), 3, 0, None, ctypes.byref(ws), ctypes.byref(nt)) == 0
+    f = ctypes.c_void_p(0x1000)
+
+    def call(**kw):
+        a = dict(dof=3, kl=f, ws=f, wsb=ws.value, rp=f, col=f, val=f, cap=nt.value, nnz=f, st=f)
+        a.update(kw)
+        return L.kb_assemble_lower_csr_dof(ctypes.byref(m), a["dof"], 0, None, a["kl"], a["ws"], a["wsb"], a["rp"],
+                                           a["col"], a["val"], a["cap"], a["nnz"], a["st"], None)
+
+    assert call(wsb=ws.value - 1) == _lib.KB_ENOSPC
+    assert call(dof=4) == _lib.KB_EINVAL
+    assert call(cap=-1) == _lib.KB_EINVAL
+    for k in ("kl", "ws", "rp", "nnz", "st"):
+        assert call(**{k: None}) == _lib.KB_EINVAL, k
+    for k in ("col", "val"):  # needed only when cap > 0
+        assert call(**{k: None}) == _lib.KB_EINVAL, k
+    m.conn = None
+    assert call() == _lib.KB_EINVAL

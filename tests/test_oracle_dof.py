@@ -19,9 +19,7 @@ def small(elem, seed):
 
 def random_klow(n_elem, nd, seed):
     """Random symmetric element matrices, packed lower (p(p+1)/2 + q)."""
-    rng = np.random.default_rng(seed)
-    T = nd * (nd + 1) // 2
-    return rng.standard_normal((n_elem, T))
+    return meshgen.element_matrices(n_elem, nd, seed)
 
 
 def unpack(k, nd):
