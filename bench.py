@@ -7,7 +7,8 @@ c log-uniform in [1e-3, 1e3], FP32 integration with FP64 Jacobian fallback.
 A step is one complete construction from device-resident E, C, c to device-resident
 row_ptr / col_idx / vals.  Prints one JSON line.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c2|c1|c5] [--prec ...]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c2|c1|c4|c5|c6] [--prec ...]
+                    [--groups G] [--dof D] [--op mass] [--adjoint]
 """
 from __future__ import annotations
 
@@ -32,6 +33,8 @@ WORKLOADS = {
     "c5": (5, "hex8 box 64^3 (262,144 elements), jitter 0.2h, c log-U[1e-1,1e1]", "fp64"),
     "c4": (4, "256 hex8 boxes, cells per axis U{8..64}, h=1/64, jitter 0.2h, c log-U[1e-2,1e2], one batched "
               "build", "fp32fb64"),
+    "c6": (6, "tet4 Kuhn 6x337^3 (229,636,518 elements, 38,614,472 nodes, 2,296,365,180 element pairs: more than "
+              "one pass indexes), jitter 0.2h, c log-U[1e-3,1e3], grouped build", "fp32fb64"),
 }
 
 
@@ -119,6 +122,8 @@ def parse():
                     help="element integrand: stiffness matrix (default) or consistent mass matrix")
     ap.add_argument("--adjoint", action="store_true",
                     help="also time the adjoint (dL/dc, dL/dX of L = sum W K, seeded N(0,1) weights), FP64")
+    ap.add_argument("--groups", type=int, default=0,
+                    help="build in this many element groups (Eq. 10; workload c6 needs at least 2, default 2)")
     ap.add_argument("--dof", type=int, default=1, choices=[1, 2, 3],
                     help="also time the assembly of k ⊗ I_dof element matrices (several DOFs per node)")
     ap.add_argument("--block", type=int, default=0, help="tuning: element tile / block size")
@@ -127,8 +132,18 @@ def parse():
     return ap.parse_args()
 
 
-def time_builds(kb, torch, mesh_dev, m, prec, steps, warmup, stage_events=True, tuning=None, op="stiffness"):
-    if isinstance(mesh_dev, kb.Batch):
+def time_builds(kb, torch, mesh_dev, m, prec, steps, warmup, stage_events=True, tuning=None, op="stiffness",
+                groups=0):
+    if groups > 1:
+        import meshgen
+
+        conn, coords, coef = mesh_dev
+        cap = meshgen.box_nnz(m.elem, m.meta["nx"], m.meta["ny"], m.meta["nz"])
+        b = kb.GroupedBuilder(m.elem, m.n_elem, m.n_node, -(-m.n_elem // groups), cap, prec=prec, tuning=tuning,
+                              op=op)
+        run = lambda ev=None: b.run(conn, coords, coef, stage_events=ev)  # noqa: E731
+        result = lambda: b.result(check=True, allow_flags=0)  # noqa: E731
+    elif isinstance(mesh_dev, kb.Batch):
         b = kb.BatchBuilder(mesh_dev, prec=prec, tuning=tuning)
         run = lambda ev=None: b.run(stage_events=ev)  # noqa: E731
         result = lambda: b.results(check=True)  # noqa: E731
@@ -312,6 +327,10 @@ def main():
         del src, dst
     cid, desc, default_prec = WORKLOADS[args.workload]
     prec = args.prec or default_prec
+    groups = args.groups if args.groups else (2 if cid == 6 else 0)
+    if groups > 1 and cid == 4:
+        print("grouped builds apply to single meshes", file=sys.stderr)
+        sys.exit(2)
     print(f"[bench] generating workload {args.workload}: {desc}", file=sys.stderr, flush=True)
     dev = torch.device("cuda:0")
     if cid == 4:
@@ -327,7 +346,8 @@ def main():
 
     tuning = kb.Tuning(block=args.block, bucket_bits=args.bucket_bits, sub_bits=args.sub_bits)
     ms, wall_ms, stages, res = time_builds(kb, torch, mesh_dev, m, prec, args.steps, args.warmup,
-                                           stage_events=not args.profile_steps, tuning=tuning, op=args.op)
+                                           stage_events=not args.profile_steps, tuning=tuning, op=args.op,
+                                           groups=groups)
     nnz = res.nnz
     print(f"[bench] {prec}: {ms:.3f} ms/step, nnz {nnz}, fallback elements {res.n_fallback}", file=sys.stderr,
           flush=True)
@@ -340,10 +360,15 @@ def main():
         "config": {"workload": desc if args.op == "stiffness" else desc + ", consistent mass matrix",
                    "n_elem": m.n_elem, "n_node": m.n_node, "nnz": nnz, "precision": prec,
                    "fp64_fallback_elements": res.n_fallback, "parallelism": "single GPU",
-                   "tuning": {"block": args.block, "bucket_bits": args.bucket_bits, "sub_bits": args.sub_bits}},
+                   "tuning": {"block": args.block, "bucket_bits": args.bucket_bits, "sub_bits": args.sub_bits},
+                   "groups": groups if groups > 1 else 1},
         "path_hbm_frac": ab["path"] / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
     }
-    if stages:
+    if stages and groups > 1:
+        # the stage events time the last group's pass only; its pairs include the carried sums
+        out["roofline"] = None
+        out["stages_ms_last_group"] = stages
+    elif stages:
         dom = max(SINGLE_KERNEL_STAGES, key=lambda k: stages[k])
         kernel = SINGLE_KERNEL_STAGES[dom] + ("_tet" if dom == "integrate" and m.elem == 4 else "")
         achieved = ab[dom] / (stages[dom] * 1e-3) / 1e9
@@ -355,7 +380,8 @@ def main():
     if not args.no_fp64 and prec != "fp64":
         ms64, _, st64, r64 = time_builds(kb, torch, mesh_dev, m, "fp64", max(3, args.steps // 2), 2,
                                          stage_events=False, tuning=kb.Tuning(bucket_bits=args.bucket_bits,
-                                                                              sub_bits=args.sub_bits), op=args.op)
+                                                                              sub_bits=args.sub_bits), op=args.op,
+                                         groups=groups)
         out["fp64"] = {"ms_per_step": ms64, "value": m.n_elem / (ms64 * 1e-3)}
         out["speedup_vs_fp64"] = ms64 / ms
         print(f"[bench] fp64: {ms64:.3f} ms/step", file=sys.stderr, flush=True)

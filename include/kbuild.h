@@ -195,6 +195,35 @@ int kb_assemble_lower_csr_dof(const kb_mesh* mesh, int dof, int prec, const kb_t
                               int64_t* nnz_dev, uint32_t* status_dev, void* stream);
 
 /*
+ * Grouped build (Eq. 10: K as the sum of the matrices of element groups, each group
+ * assembled while the next is integrated).  Elements [g*G, (g+1)*G) form group g; one
+ * pass per group integrates the group and, in the same pass, reads back the sums of
+ * the groups before it (a lower CSR carried in the output arrays and the workspace) as
+ * pairs beside the group's own, so the sums grow group by group and the last pass
+ * leaves K in the outputs.  Each carried entry is held as its rounded value plus the
+ * rounded residual (together about twice the value type's precision).  Each pass
+ * truncates its values at its own fixed-point scale (2^-94 of its largest value), so
+ * the result can differ from a single-pass build only where that truncation matters:
+ * within one rounding of an entry, or a few units of 2^-94 of the largest entry
+ * (measured: most meshes bit for bit; tiny entries of meshes with a wide coefficient
+ * range may differ in the last bit).  One pass's pairs are
+ * G * nen*(nen+1)/2 + 2 * cap, which must stay below 2^31: grouping builds meshes whose
+ * n_elem * nen*(nen+1)/2 exceeds what one pass indexes, as long as nnz stays below 2^31.
+ *   group_elems  G >= 1 (G >= n_elem: a single pass, as kb_build_lower_csr)
+ *   cap          capacity of col_idx / vals and of the carried sums: at least the final
+ *                nnz (the sums only grow), else KB_F_CAPACITY and the result is void
+ *   other arguments as for kb_build_lower_csr (both operators; status accumulates over
+ *   the groups; stage events, if given, time the last group's pass)
+ * kb_plan_grouped sizes the workspace (host only).  Errors: KB_EINVAL (group_elems < 1,
+ * a bad argument), KB_ERANGE (a pass's pairs or cap beyond int32 indexing), KB_ENOSPC.
+ */
+int kb_plan_grouped(const kb_mesh* mesh, int prec, const kb_tuning* tuning, int64_t group_elems, int64_t cap,
+                    size_t* ws_bytes);
+int kb_build_lower_csr_grouped(const kb_mesh* mesh, int prec, const kb_tuning* tuning, int64_t group_elems, void* ws,
+                               size_t ws_bytes, int32_t* row_ptr, int32_t* col_idx, void* vals, int64_t cap,
+                               int64_t* nnz_dev, uint32_t* status_dev, void* stream);
+
+/*
  * Batches.  Many independent meshes of one element type, built by one enqueued sequence
  * of kernels (no host synchronisation, so the whole call can be captured in a HIP graph).
  * The meshes are packed back to back: mesh m owns elements [elem_off[m], elem_off[m+1])

@@ -179,12 +179,13 @@ CONFIG_NAMES = {
     3: "tet4 Kuhn 6x150^3, jitter 0.2h, random node+element numbering, c log-U[1e-3,1e3]",
     4: "batch of 256 hex8 boxes, cells per axis U{8..64}, h=1/64, jitter 0.2h, c log-U[1e-2,1e2]",
     5: "hex8 box 64^3, jitter 0.2h, c log-U[1e-1,1e1], FP64 (+ seeded normal loss weights)",
+    6: "tet4 Kuhn 6x337^3, jitter 0.2h, c log-U[1e-3,1e3] (more element pairs than one pass indexes)",
 }
-CONFIG_FULL_N = {1: 10, 2: 100, 3: 150, 5: 64}
+CONFIG_FULL_N = {1: 10, 2: 100, 3: 150, 5: 64, 6: 337}
 
 
 def config_mesh(cid: int, n: int | None = None) -> Mesh:
-    """Mesh of workload ``cid`` (1, 2, 3 or 5); ``n`` shrinks the cube for tests."""
+    """Mesh of workload ``cid`` (1, 2, 3, 5 or 6); ``n`` shrinks the cube for tests."""
     n = CONFIG_FULL_N[cid] if n is None else n
     if cid == 1:
         return box_mesh(8, n, jitter=0.2, coef=1.0, seed=1)
@@ -194,6 +195,8 @@ def config_mesh(cid: int, n: int | None = None) -> Mesh:
         return box_mesh(4, n, jitter=0.2, coef=(1e-3, 1e3), permute_nodes=True, permute_elems=True, seed=3)
     if cid == 5:
         return box_mesh(8, n, jitter=0.2, coef=(1e-1, 1e1), seed=5)
+    if cid == 6:
+        return box_mesh(4, n, jitter=0.2, coef=(1e-3, 1e3), seed=7)
     raise ValueError(f"config {cid} is not a single mesh")
 
 
@@ -227,3 +230,16 @@ def element_matrices(n_elem: int, nd: int, seed: int = 6) -> np.ndarray:
     """Seeded N(0,1) packed lower triangles [n_elem, nd(nd+1)/2] of symmetric element
     matrices (inputs of the assembly-only paths; no physics)."""
     return streams(seed)[5].standard_normal((n_elem, nd * (nd + 1) // 2))
+
+
+def box_nnz(elem: int, nx: int, ny: int, nz: int) -> int:
+    """Lower nnz of a structured box: its nodes plus every node pair sharing an element.
+    Bricks: axis edges, both diagonals of every face, the four body diagonals of a cell.
+    Kuhn tetrahedra: axis edges, one diagonal per face, one body diagonal per cell."""
+    X, Y, Z = nx + 1, ny + 1, nz + 1
+    axis = nx * Y * Z + X * ny * Z + X * Y * nz
+    faces = nx * ny * Z + nx * Y * nz + X * ny * nz
+    cells = nx * ny * nz
+    if elem == 8:
+        return X * Y * Z + axis + 2 * faces + 4 * cells
+    return X * Y * Z + axis + faces + cells

@@ -240,6 +240,67 @@ def assemble_lower_csr(conn, n_node: int, klow, elem: int, prec="fp64", tuning: 
     return b.result(check=check, allow_flags=allow_flags)
 
 
+# ---- grouped builds (Eq. 10) -------------------------------------------------------------
+def plan_grouped(elem: int, n_elem: int, n_node: int, group_elems: int, cap: int, prec="fp32fb64",
+                 tuning: Tuning | None = None, op="stiffness") -> int:
+    """Workspace bytes of a grouped build."""
+    ws = ctypes.c_size_t(0)
+    m = _mesh(elem, n_elem, n_node, op=op)
+    tu = (tuning or Tuning()).to_c()
+    _check(_lib.lib().kb_plan_grouped(ctypes.byref(m), _prec(prec), ctypes.byref(tu), int(group_elems), int(cap),
+                                      ctypes.byref(ws)), "kb_plan_grouped")
+    return int(ws.value)
+
+
+class GroupedBuilder:
+    """Reusable grouped build (elements in groups of ``group_elems``, one pass each;
+    ``cap`` bounds the final nnz).  ``run`` enqueues the passes and allocates nothing."""
+
+    def __init__(self, elem: int, n_elem: int, n_node: int, group_elems: int, cap: int, prec="fp32fb64",
+                 tuning: Tuning | None = None, device="cuda", op="stiffness"):
+        self.elem, self.n_elem, self.n_node = int(elem), int(n_elem), int(n_node)
+        self.group, self.cap = int(group_elems), int(cap)
+        self.prec, self.op = _prec(prec), _op(op)
+        self.tuning = tuning or Tuning()
+        self.ws_bytes = plan_grouped(elem, n_elem, n_node, self.group, self.cap, self.prec, self.tuning, self.op)
+        dev = torch.device(device)
+        self.ws = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=dev)
+        self.row_ptr = torch.empty(self.n_node + 1, dtype=torch.int32, device=dev)
+        self.col_idx = torch.empty(max(self.cap, 1), dtype=torch.int32, device=dev)
+        self.vals = torch.empty(max(self.cap, 1), dtype=value_dtype(self.prec), device=dev)
+        self.nnz_dev = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.status = torch.zeros(KB_STATUS_WORDS, dtype=torch.int32, device=dev)
+
+    def run(self, conn, coords, coef, stage_events=None, stream=None):
+        s = stream if stream is not None else torch.cuda.current_stream()
+        ev = None
+        if stage_events is not None:
+            arr = (ctypes.c_void_p * len(stage_events))(*[int(e) for e in stage_events])
+            self._ev_keep = arr
+            ev = ctypes.cast(arr, ctypes.c_void_p)
+        tu = self.tuning.to_c(ev)
+        m = _mesh(self.elem, self.n_elem, self.n_node, conn, coords, coef, self.op)
+        rc = _lib.lib().kb_build_lower_csr_grouped(ctypes.byref(m), self.prec, ctypes.byref(tu), self.group,
+                                                   _ptr(self.ws), self.ws_bytes, _ptr(self.row_ptr),
+                                                   _ptr(self.col_idx), _ptr(self.vals), self.cap, _ptr(self.nnz_dev),
+                                                   _ptr(self.status), ctypes.c_void_p(s.cuda_stream))
+        _check(rc, "kb_build_lower_csr_grouped")
+
+    result = Builder.result
+
+
+def build_lower_csr_grouped(conn, coords, coef, elem: int, group_elems: int, cap: int, prec="fp32fb64",
+                            tuning: Tuning | None = None, check=True, allow_flags: int = 0,
+                            op="stiffness") -> LowerCSR:
+    """Grouped construction (Eq. 10): elements in groups of ``group_elems``, the running
+    sums carried from group to group; ``cap`` must be at least the final nnz."""
+    _validate_mesh(conn, coords, coef, elem)
+    b = GroupedBuilder(elem, conn.shape[0], coords.shape[0], group_elems, cap, prec, tuning, device=conn.device,
+                       op=op)
+    b.run(conn, coords, coef)
+    return b.result(check=check, allow_flags=allow_flags)
+
+
 def integrate_lower(conn, coords, coef, elem: int, prec="fp64", tuning: Tuning | None = None, check=True,
                     allow_flags: int = 0, op="stiffness"):
     """Per-element packed lower triangles [n_elem, nen(nen+1)/2] (Alg. 2 only)."""

@@ -46,10 +46,11 @@ struct Plan {
   int tile = 0;                        // elements (= threads) per pass-1 workgroup
   int cus = 256;                       // compute units of the current device (launch time)
   int64_t ntiles = 0, nsub = 0, nhist = 0, nseg_max = 0;
+  int64_t csr_cap = 0, ntiles_csr = 0;  // running sums read back as pairs (grouped builds)
   size_t lds1 = 0, lds2 = 0;
   // workspace offsets
   size_t o_coords4 = 0, o_hist = 0, o_histT = 0, o_part = 0, o_total = 0, o_bstart = 0, o_segbase = 0, o_hist2 = 0, o_seg2b = 0, o_emax = 0,
-         o_klow = 0, o_dconn = 0, o_row1 = 0, o_col1 = 0, o_val1 = 0, o_key2 = 0, o_val2 = 0, o_sbb = 0, o_rowoff = 0, o_usub = 0, o_ubase = 0,
+         o_klow = 0, o_dconn = 0, o_tres = 0, o_row1 = 0, o_col1 = 0, o_val1 = 0, o_key2 = 0, o_val2 = 0, o_sbb = 0, o_rowoff = 0, o_usub = 0, o_ubase = 0,
          total = 0;
 };
 
@@ -80,7 +81,9 @@ int ilog2_ceil(int64_t x) {
 
 // dof > 1: element matrices with dof components per node are assembled as elements of
 // nen * dof "nodes" (global DOF dof * E_a + i); nen and nn below are those of that view
-int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p, int dof = 1) {
+// csr_cap > 0: each pass also reads back up to csr_cap entries of running sums as two
+// pairs each (value and residual), and writes residuals (grouped builds)
+int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p, int dof = 1, int64_t csr_cap = 0) {
   if (!m) return KB_EINVAL;
   if (m->elem != KB_HEX8 && m->elem != KB_TET4) return KB_EINVAL;
   if (prec != KB_FP64 && prec != KB_FP32 && prec != KB_FP32_FB64) return KB_EINVAL;
@@ -95,8 +98,10 @@ int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p, int dof 
   if (m->n_node >= (int64_t)INT32_MAX / dof) return KB_ERANGE;
   p->nn = m->n_node * dof;
   if (p->nn >= (int64_t)INT32_MAX) return KB_ERANGE;
-  if (p->nel > (int64_t)INT32_MAX / p->te) return KB_ERANGE;
-  p->T = p->nel * p->te;
+  if (csr_cap < 0) return KB_EINVAL;
+  if (p->nel > (int64_t)INT32_MAX / p->te || csr_cap > ((int64_t)INT32_MAX - p->nel * p->te) / 2) return KB_ERANGE;
+  p->csr_cap = csr_cap;
+  p->T = p->nel * p->te + 2 * csr_cap;  // pairs of one pass
   p->vbytes = prec == KB_FP64 ? 8 : 4;
   int bucket_bits = 0, sub_bits = 0;
   if (tu) {
@@ -118,8 +123,10 @@ int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p, int dof 
   // of elements sharing an entry (about 7 for tetrahedra, 2.5 for bricks)
   p->colbits = 1;
   while (((int64_t)1 << p->colbits) < p->nn) ++p->colbits;
-  const double avg = p->nn > 0 ? (double)p->T / (double)p->nn : 1.0;
-  const double u_row = std::max(1.0, avg / (m->elem == KB_TET4 ? 7.4 : 2.5));
+  // (running sums read back bring up to csr_cap distinct entries of their own)
+  const double avg = p->nn > 0 ? (double)(p->nel * p->te) / (double)p->nn : 1.0;
+  const double u_row = std::max(1.0, avg / (m->elem == KB_TET4 ? 7.4 : 2.5) +
+                                         (p->nn > 0 ? (double)csr_cap / (double)p->nn : 0.0));
   const int s2_max = std::min(8, 31 - p->colbits);
   if (sub_bits) {
     if (sub_bits > s2_max) return KB_EINVAL;
@@ -161,7 +168,10 @@ int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p, int dof 
               (size_t)p->tile * p->nen * 12 + 4 * (size_t)p->tile + 2 * (size_t)p->te;
   }
   p->ntiles = div_up(p->nel, p->tile);
-  p->nhist = (int64_t)p->nb * p->ntiles;
+  p->ntiles_csr = div_up(csr_cap, kCsrTile);
+  p->nhist = (int64_t)p->nb * (p->ntiles + p->ntiles_csr);
+  if (csr_cap > 0 && 2 * (size_t)kCsrTile * (8 + p->vbytes) + 2 * 4 * (size_t)p->nb + 4 * (256 / 64 + 2) > 163840)
+    return KB_EINVAL;
   p->nseg_max = div_up(p->T, kSeg) + p->nb;
   p->lds2 = (size_t)kSeg * (p->vbytes + 4 + 2) + 2 * 4 * (size_t)p->p2 + 4 * (kSegThreads / 64 + 1);
   if (p->lds1 > 163840 || p->lds2 > 163840) return KB_EINVAL;
@@ -187,6 +197,7 @@ int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p, int dof 
   // mass builds integrate into element values first, then assemble them
   p->o_klow = take(p->op == KB_OP_MASS && p->dof == 1 ? p->vbytes * T : 0);
   p->o_dconn = take(p->dof > 1 ? 4 * (size_t)p->nen * (size_t)p->nel : 0);  // expanded connectivity
+  p->o_tres = take(csr_cap > 0 ? p->vbytes * T : 0);  // residuals of the reduced entries
   p->o_row1 = take(2 * T);
   p->o_col1 = take(4 * T);
   p->o_val1 = take(p->vbytes * T);
@@ -315,9 +326,46 @@ int launch_pass1(const Plan& p, const kb_mesh* m, const void* klow, unsigned cha
   }
 }
 
+// Running sums of a grouped build: read back as a second source of pairs (in), and the
+// pass's entries written with their residuals and rows (out).
+struct Carry {
+  bool first = true;              // first pass: the status words are initialised
+  const int32_t* rows = nullptr;  // in: rows, columns, values, residuals of the entries
+  const int32_t* cols = nullptr;
+  const void* vals = nullptr;
+  const void* res = nullptr;
+  const int64_t* nnz = nullptr;   // in: number of entries (device); nullptr: no input
+  void* res_out = nullptr;        // out: residuals and rows of the pass's entries
+  int32_t* rows_out = nullptr;
+};
+
+template <typename V, bool RES>
+void launch_pass3(const Plan& p, uint32_t* key2, V* val2, uint32_t* sbb, uint32_t* emax, int32_t* tcol, V* tval,
+                  V* tres, uint32_t* rowoff, uint32_t* usub, hipStream_t s) {
+  const unsigned g3 = (unsigned)p.nsub;
+  switch (p.ht) {
+    case 512:
+      k_pass3<V, 512, RES><<<g3, 256, 0, s>>>(key2, val2, sbb, p.s2, p.colbits, p.nn, emax, tcol, tval, tres, rowoff,
+                                              usub);
+      break;
+    case 1024:
+      k_pass3<V, 1024, RES><<<g3, 256, 0, s>>>(key2, val2, sbb, p.s2, p.colbits, p.nn, emax, tcol, tval, tres,
+                                               rowoff, usub);
+      break;
+    case 2048:
+      k_pass3<V, 2048, RES><<<g3, 256, 0, s>>>(key2, val2, sbb, p.s2, p.colbits, p.nn, emax, tcol, tval, tres,
+                                               rowoff, usub);
+      break;
+    default:
+      k_pass3<V, 4096, RES><<<g3, 256, 0, s>>>(key2, val2, sbb, p.s2, p.colbits, p.nn, emax, tcol, tval, tres,
+                                               rowoff, usub);
+      break;
+  }
+}
+
 template <typename V>
 int assemble_tail(const Plan& p, unsigned char* ws, int32_t* row_ptr, int32_t* col_idx, V* vals, int64_t cap,
-                  int64_t* nnz_dev, uint32_t* status, Events& ev, hipStream_t s) {
+                  int64_t* nnz_dev, uint32_t* status, Events& ev, hipStream_t s, const Carry* cr) {
   auto* bstart = (uint32_t*)(ws + p.o_bstart);
   auto* segbase = (uint32_t*)(ws + p.o_segbase);
   auto* hist2 = (uint32_t*)(ws + p.o_hist2);
@@ -355,34 +403,25 @@ int assemble_tail(const Plan& p, unsigned char* ws, int32_t* row_ptr, int32_t* c
                                       p.colbits, key2, val2);
     KB_LAUNCH_CHECK();
   }
+  auto* tres = (V*)(ws + p.o_tres);
   KB_TRY(ev.rec(KB_STAGE_REDUCE));
   if (p.nsub > 0) {
-    const unsigned g3 = (unsigned)p.nsub;
-    switch (p.ht) {
-      case 512:
-        k_pass3<V, 512><<<g3, 256, 0, s>>>(key2, val2, sbb, p.s2, p.colbits, p.nn, emax, tcol, tval, rowoff,
-                                           usub);
-        break;
-      case 1024:
-        k_pass3<V, 1024><<<g3, 256, 0, s>>>(key2, val2, sbb, p.s2, p.colbits, p.nn, emax, tcol, tval, rowoff,
-                                            usub);
-        break;
-      case 2048:
-        k_pass3<V, 2048><<<g3, 256, 0, s>>>(key2, val2, sbb, p.s2, p.colbits, p.nn, emax, tcol, tval, rowoff,
-                                            usub);
-        break;
-      default:
-        k_pass3<V, 4096><<<g3, 256, 0, s>>>(key2, val2, sbb, p.s2, p.colbits, p.nn, emax, tcol, tval, rowoff,
-                                            usub);
-        break;
-    }
+    if (cr)
+      launch_pass3<V, true>(p, key2, val2, sbb, emax, tcol, tval, tres, rowoff, usub, s);
+    else
+      launch_pass3<V, false>(p, key2, val2, sbb, emax, tcol, tval, nullptr, rowoff, usub, s);
     KB_LAUNCH_CHECK();
   }
   KB_TRY(ev.rec(KB_STAGE_COMPRESS));
   KB_TRY(scan((const int32_t*)usub, p.nsub, part, (int32_t*)ubase, nnz_dev, s));
   if (p.nsub > 0) {
-    k_final<V><<<(unsigned)div_up(p.nsub, 4), 256, 0, s>>>(sbb, ubase, tcol, tval, rowoff, p.s2, p.nn, p.nsub, row_ptr,
-                                                           col_idx, vals, cap, status);
+    const unsigned gf = (unsigned)div_up(p.nsub, 4);
+    if (cr)
+      k_final<V, true><<<gf, 256, 0, s>>>(sbb, ubase, tcol, tval, tres, rowoff, p.s2, p.nn, p.nsub, row_ptr, col_idx,
+                                          vals, (V*)cr->res_out, cr->rows_out, cap, status);
+    else
+      k_final<V><<<gf, 256, 0, s>>>(sbb, ubase, tcol, tval, nullptr, rowoff, p.s2, p.nn, p.nsub, row_ptr, col_idx,
+                                    vals, nullptr, nullptr, cap, status);
     KB_LAUNCH_CHECK();
   } else {
     k_scan_empty<<<1, 1, 0, s>>>(row_ptr, nullptr);
@@ -395,7 +434,7 @@ int assemble_tail(const Plan& p, unsigned char* ws, int32_t* row_ptr, int32_t* c
 template <int NEN, Prec P>
 int build_impl(const Plan& p, const kb_mesh* m, const void* klow, unsigned char* ws, int32_t* row_ptr,
                int32_t* col_idx, void* vals, int64_t cap, int64_t* nnz_dev, uint32_t* status, Events& ev,
-               hipStream_t s) {
+               hipStream_t s, const Carry* cr = nullptr) {
   using V = typename PrecTraits<P>::V;
   auto* hist = (uint32_t*)(ws + p.o_hist);
   auto* histT = (uint32_t*)(ws + p.o_histT);
@@ -404,9 +443,14 @@ int build_impl(const Plan& p, const kb_mesh* m, const void* klow, unsigned char*
   auto* bstart = (uint32_t*)(ws + p.o_bstart);
   auto* segbase = (uint32_t*)(ws + p.o_segbase);
 
+  // tiles of running sums read back (grouped builds) follow the element tiles
+  const int64_t ntc = (cr && cr->nnz && p.nb > 0) ? p.ntiles_csr : 0;
+  const int64_t nt_all = p.ntiles + ntc;
   KB_TRY(ev.rec(KB_STAGE_INIT));
-  k_init_status<<<1, 64, 0, s>>>(status, nnz_dev);
-  KB_LAUNCH_CHECK();
+  if (!cr || cr->first) {
+    k_init_status<<<1, 64, 0, s>>>(status, nnz_dev);
+    KB_LAUNCH_CHECK();
+  }
   k_fill_i32<<<1, 64, 0, s>>>((int32_t*)(ws + p.o_emax), 1, 0);
   KB_LAUNCH_CHECK();
 
@@ -418,13 +462,18 @@ int build_impl(const Plan& p, const kb_mesh* m, const void* klow, unsigned char*
         m->conn, p.nel, p.nn, p.tile, nb > 0 ? p.s1 : 30, nb, hist, status);
     KB_LAUNCH_CHECK();
   }
+  if (ntc > 0) {
+    k_hist_csr<<<(unsigned)ntc, 256, 4 * (size_t)p.nb, s>>>(cr->rows, cr->nnz, p.csr_cap, p.nn, p.s1, p.nb,
+                                                            hist + p.ntiles * p.nb);
+    KB_LAUNCH_CHECK();
+  }
   KB_TRY(ev.rec(KB_STAGE_OFFSETS));
   if (p.nb > 0) {
-    KB_TRY(transpose(hist, histT, p.ntiles, p.nb, s));  // -> [nb][ntiles]
-    KB_TRY(scan((const int32_t*)histT, p.nhist, part, (int32_t*)histT, total, s));
-    k_bucket_starts<<<grid_for(p.nb + 1, 256), 256, 0, s>>>(histT, p.ntiles, p.nb, total, bstart);
+    KB_TRY(transpose(hist, histT, nt_all, p.nb, s));  // -> [nb][tiles]
+    KB_TRY(scan((const int32_t*)histT, p.nb * nt_all, part, (int32_t*)histT, total, s));
+    k_bucket_starts<<<grid_for(p.nb + 1, 256), 256, 0, s>>>(histT, nt_all, p.nb, total, bstart);
     KB_LAUNCH_CHECK();
-    KB_TRY(transpose(histT, hist, p.nb, p.ntiles, s));  // -> [ntiles][nb]
+    KB_TRY(transpose(histT, hist, p.nb, nt_all, s));  // -> [tiles][nb]
     k_segments<<<1, 256, 0, s>>>(bstart, p.nb, kSeg, segbase);
     KB_LAUNCH_CHECK();
   }
@@ -455,21 +504,69 @@ int build_impl(const Plan& p, const kb_mesh* m, const void* klow, unsigned char*
       return KB_EINVAL;  // several DOFs per node: values are always given
     }
   }
-  return assemble_tail<V>(p, ws, row_ptr, col_idx, (V*)vals, cap, nnz_dev, status, ev, s);
+  if (ntc > 0) {
+    const size_t lds = 2 * (size_t)kCsrTile * (8 + sizeof(V)) + 2 * 4 * (size_t)p.nb + 4 * (256 / 64 + 2);
+    if (!set_lds(k_pass1_csr<V>, lds)) return KB_EHIP;
+    k_pass1_csr<V><<<(unsigned)ntc, 256, lds, s>>>(cr->rows, cr->cols, (const V*)cr->vals, (const V*)cr->res, cr->nnz,
+                                                   p.csr_cap, p.nn, p.s1, p.nb, hist + p.ntiles * p.nb,
+                                                   (uint16_t*)(ws + p.o_row1), (uint32_t*)(ws + p.o_col1),
+                                                   (V*)(ws + p.o_val1), (uint32_t*)(ws + p.o_emax));
+    KB_LAUNCH_CHECK();
+  }
+  return assemble_tail<V>(p, ws, row_ptr, col_idx, (V*)vals, cap, nnz_dev, status, ev, s, cr);
 }
 
 template <int NEN>
 int dispatch_build(const Plan& p, const kb_mesh* m, const void* klow, unsigned char* ws, int32_t* row_ptr,
                    int32_t* col_idx, void* vals, int64_t cap, int64_t* nnz_dev, uint32_t* status, Events& ev,
-                   hipStream_t s) {
+                   hipStream_t s, const Carry* cr = nullptr) {
   switch (p.prec) {
     case KB_FP64:
-      return build_impl<NEN, Prec::F64>(p, m, klow, ws, row_ptr, col_idx, vals, cap, nnz_dev, status, ev, s);
+      return build_impl<NEN, Prec::F64>(p, m, klow, ws, row_ptr, col_idx, vals, cap, nnz_dev, status, ev, s, cr);
     case KB_FP32:
-      return build_impl<NEN, Prec::F32>(p, m, klow, ws, row_ptr, col_idx, vals, cap, nnz_dev, status, ev, s);
+      return build_impl<NEN, Prec::F32>(p, m, klow, ws, row_ptr, col_idx, vals, cap, nnz_dev, status, ev, s, cr);
     default:
-      return build_impl<NEN, Prec::F32FB>(p, m, klow, ws, row_ptr, col_idx, vals, cap, nnz_dev, status, ev, s);
+      return build_impl<NEN, Prec::F32FB>(p, m, klow, ws, row_ptr, col_idx, vals, cap, nnz_dev, status, ev, s, cr);
   }
+}
+
+// Grouped build workspace: one pass's (the largest group plus the running sums read
+// back), then the second set of running sums (CSR, residuals, rows, count) and the
+// residuals and rows of the caller's set.  Passes alternate between the two sets so
+// that the last one writes the caller's arrays.
+struct GroupPlan {
+  Plan p;
+  int64_t group = 0, n_groups = 0;
+  size_t o_rpB = 0, o_colB = 0, o_valB = 0, o_resB = 0, o_rowsB = 0, o_nnzB = 0, o_resA = 0, o_rowsA = 0, total = 0;
+};
+
+int make_group_plan(const kb_mesh* m, int prec, const kb_tuning* tu, int64_t group_elems, int64_t cap,
+                    GroupPlan* gp) {
+  if (!m || group_elems < 1 || cap < 0 || m->n_elem < 0) return KB_EINVAL;
+  if (m->op != KB_OP_STIFFNESS && m->op != KB_OP_MASS) return KB_EINVAL;
+  if (cap >= (int64_t)INT32_MAX) return KB_ERANGE;
+  gp->group = std::min<int64_t>(group_elems, std::max<int64_t>(m->n_elem, 1));
+  gp->n_groups = std::max<int64_t>(1, div_up(m->n_elem, gp->group));
+  kb_mesh g = *m;
+  g.n_elem = std::min<int64_t>(gp->group, m->n_elem);
+  KB_TRY(make_plan(&g, prec, tu, &gp->p, 1, gp->n_groups > 1 ? cap : 0));
+  size_t off = gp->p.total;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + (bytes > 0 ? bytes : 1));
+    return o;
+  };
+  const size_t c = gp->n_groups > 1 ? (size_t)cap : 0, vb = gp->p.vbytes;
+  gp->o_rpB = take(gp->n_groups > 1 ? 4 * ((size_t)gp->p.nn + 1) : 0);
+  gp->o_colB = take(4 * c);
+  gp->o_valB = take(vb * c);
+  gp->o_resB = take(vb * c);
+  gp->o_rowsB = take(4 * c);
+  gp->o_nnzB = take(8);
+  gp->o_resA = take(vb * c);
+  gp->o_rowsA = take(4 * c);
+  gp->total = off;
+  return KB_OK;
 }
 
 template <int NEN, Prec P>
@@ -660,6 +757,77 @@ int kb_assemble_lower_csr_dof(const kb_mesh* mesh, int dof, int prec, const kb_t
     default:
       return KB_EINVAL;
   }
+}
+
+int kb_plan_grouped(const kb_mesh* mesh, int prec, const kb_tuning* tuning, int64_t group_elems, int64_t cap,
+                    size_t* ws_bytes) {
+  GroupPlan gp;
+  KB_TRY(make_group_plan(mesh, prec, tuning, group_elems, cap, &gp));
+  if (ws_bytes) *ws_bytes = gp.total;
+  return KB_OK;
+}
+
+int kb_build_lower_csr_grouped(const kb_mesh* mesh, int prec, const kb_tuning* tuning, int64_t group_elems, void* ws,
+                               size_t ws_bytes, int32_t* row_ptr, int32_t* col_idx, void* vals, int64_t cap,
+                               int64_t* nnz_dev, uint32_t* status_dev, void* stream) {
+  GroupPlan gp;
+  KB_TRY(make_group_plan(mesh, prec, tuning, group_elems, cap, &gp));
+  KB_TRY(check_mesh_ptrs(mesh, true));
+  if (!row_ptr || !nnz_dev || !status_dev) return KB_EINVAL;
+  if (cap > 0 && (!col_idx || !vals)) return KB_EINVAL;
+  if (ws_bytes < gp.total) return KB_ENOSPC;
+  if (!ws) return KB_EINVAL;
+  KB_TRY(device_cus(&gp.p.cus));
+  auto* w = (unsigned char*)ws;
+  auto s = (hipStream_t)stream;
+  Events none{nullptr, s};
+  Events ev{tuning ? tuning->stage_events : nullptr, s};
+  // the two sets of running sums: A = the caller's arrays, B = workspace
+  struct Set {
+    int32_t* rp;
+    int32_t* col;
+    void* val;
+    void* res;
+    int32_t* rows;
+    int64_t* nnz;
+  };
+  const Set A{row_ptr, col_idx, vals, w + gp.o_resA, (int32_t*)(w + gp.o_rowsA), nnz_dev};
+  const Set B{(int32_t*)(w + gp.o_rpB), (int32_t*)(w + gp.o_colB), w + gp.o_valB, w + gp.o_resB,
+              (int32_t*)(w + gp.o_rowsB), (int64_t*)(w + gp.o_nnzB)};
+  for (int64_t g = 0; g < gp.n_groups; ++g) {
+    // this group's elements as a mesh; all nodes
+    kb_mesh mg = *mesh;
+    const int64_t e0 = g * gp.group;
+    mg.n_elem = std::min<int64_t>(gp.group, mesh->n_elem - e0);
+    if (mg.n_elem < 0) mg.n_elem = 0;
+    if (mesh->n_elem > 0) {
+      mg.conn = mesh->conn + e0 * mesh->elem;
+      mg.coef = mesh->coef + e0;
+    }
+    Plan p = gp.p;
+    p.nel = mg.n_elem;
+    p.ntiles = div_up(p.nel, p.tile);
+    const Set& out = ((gp.n_groups - 1 - g) % 2 == 0) ? A : B;
+    const Set& in = (&out == &A) ? B : A;
+    Carry cr;
+    cr.first = g == 0;
+    if (g > 0) {
+      cr.rows = in.rows;
+      cr.cols = in.col;
+      cr.vals = in.val;
+      cr.res = in.res;
+      cr.nnz = in.nnz;
+    }
+    cr.res_out = out.res;
+    cr.rows_out = out.rows;
+    const Carry* crp = gp.n_groups > 1 ? &cr : nullptr;
+    Events& e = g == gp.n_groups - 1 ? ev : none;
+    if (p.nen == 8)
+      KB_TRY(dispatch_build<8>(p, &mg, nullptr, w, out.rp, out.col, out.val, cap, out.nnz, status_dev, e, s, crp));
+    else
+      KB_TRY(dispatch_build<4>(p, &mg, nullptr, w, out.rp, out.col, out.val, cap, out.nnz, status_dev, e, s, crp));
+  }
+  return KB_OK;
 }
 
 int kb_plan_batched(const kb_batch* batch, int prec, const kb_tuning* tuning, size_t* ws_bytes,

@@ -210,6 +210,18 @@ __device__ __forceinline__ double from_fixed(uint64_t lo, uint64_t hi, int F) {
   return from_fixed_as<double>(lo, hi, F);
 }
 
+// What V's rounding h of an exact value left out, rounded to V: h + residual holds the
+// value to about twice V's precision.  h * 2^F is an integer (the value rounded), so its
+// fixed-point form is exact and the difference is exact before its one rounding.
+template <typename V>
+__device__ __forceinline__ V fixed_residual(uint64_t lo, uint64_t hi, int F, V h) {
+  uint64_t a, b;
+  to_fixed((double)h, F, a, b);
+  const uint64_t dl = lo - a;
+  const uint64_t dh = hi - b - (lo < a ? 1ull : 0ull);
+  return from_fixed_as<V>(dl, dh, F);
+}
+
 // ---------------------------------------------------------------------- histogram
 // Per tile of `te` elements: pairs per bucket (row >> s1), written tile-major
 // hist[t * nb + b].  Flags index errors; invalid elements contribute nothing.
@@ -606,6 +618,88 @@ __global__ __launch_bounds__(256) void k_pass1_wide(const int32_t* __restrict__ 
   pass1_write(sm, n_items, s1, NT, orow, ocol, oval);
 }
 
+// ----------------------------------------------------- running sums as a source
+// A grouped build carries the sums of the groups done so far as a lower CSR (entries in
+// row order, with rows[], residuals res[] and nnz in device memory).  The next group's
+// pass reads them back as pairs (row, col, value) and (row, col, residual) next to its
+// elements' pairs.  Tiles of kCsrTile entries follow the element tiles.  The entries
+// are read only if they were written (nnz <= cap); rows outside [0, n_node) are skipped
+// (both kernels apply the same test, so counts and writes agree).
+constexpr int kCsrTile = 2048;
+
+__device__ __forceinline__ int64_t csr_entries(const int64_t* nnz_dev, int64_t cap) {
+  const int64_t n = *nnz_dev;
+  return (n >= 0 && n <= cap) ? n : 0;
+}
+
+__global__ __launch_bounds__(256) void k_hist_csr(const int32_t* __restrict__ rows, const int64_t* __restrict__ nnz_dev,
+                                                  int64_t cap, int64_t n_node, int s1, int nb,
+                                                  uint32_t* __restrict__ hist) {
+  extern __shared__ uint32_t s_h[];  // [nb]
+  const int64_t t = blockIdx.x;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) s_h[b] = 0;
+  __syncthreads();
+  const int64_t n = csr_entries(nnz_dev, cap);
+  const int64_t e0 = t * kCsrTile, e1 = e0 + kCsrTile < n ? e0 + kCsrTile : n;
+  for (int64_t i = e0 + threadIdx.x; i < e1; i += blockDim.x) {
+    const int32_t r = rows[i];
+    if (r >= 0 && r < n_node) atomicAdd(&s_h[r >> s1], 2u);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) hist[t * nb + b] = s_h[b];
+}
+
+template <typename V>
+__global__ __launch_bounds__(256) void k_pass1_csr(const int32_t* __restrict__ rows, const int32_t* __restrict__ cols,
+                                                 const V* __restrict__ vals, const V* __restrict__ res,
+                                                 const int64_t* __restrict__ nnz_dev, int64_t cap, int64_t n_node,
+                                                 int s1, int nb, const uint32_t* __restrict__ off1,
+                                                 uint16_t* __restrict__ orow, uint32_t* __restrict__ ocol,
+                                                 V* __restrict__ oval, uint32_t* __restrict__ emax) {
+  constexpr int NT = 256, PER = kCsrTile / NT;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const Pass1Smem<V, NT> sm(smem, 2 * kCsrTile, nb);
+  const int64_t t = blockIdx.x;
+  for (int b = threadIdx.x; b < nb; b += NT) {
+    sm.cnt[b] = 0;
+    sm.base[b] = off1[t * nb + b];
+  }
+  if (threadIdx.x == 0) *sm.emax = 0;
+  __syncthreads();
+  const int64_t n = csr_entries(nnz_dev, cap);
+  const int64_t e0 = t * kCsrTile;
+  int32_t r[PER];
+  uint32_t q[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int64_t i = e0 + u * NT + threadIdx.x;
+    r[u] = i < n ? rows[i] : -1;
+    if (r[u] >= n_node) r[u] = -1;
+    if (r[u] >= 0) q[u] = atomicAdd(&sm.cnt[r[u] >> s1], 2u);
+  }
+  __syncthreads();
+  const uint32_t n_items = block_scan_array(sm.cnt, nb, sm.scan);
+  uint32_t em = 0;
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    if (r[u] < 0) continue;
+    const int64_t i = e0 + u * NT + threadIdx.x;
+    const uint32_t pos = sm.cnt[r[u] >> s1] + q[u];
+    const uint64_t key = (uint64_t)(uint32_t)r[u] << 32 | (uint32_t)cols[i];
+    const V h = vals[i];
+    sm.key[pos] = key;
+    sm.val[pos] = h;
+    sm.key[pos + 1] = key;
+    sm.val[pos + 1] = res[i];
+    const uint32_t ep = (uint32_t)biased_exponent((double)h);  // |res| <= |h|
+    em = (ep > em && ep < 0x7FF) ? ep : em;
+  }
+  if (em) atomicMax(sm.emax, em);
+  __syncthreads();
+  if (threadIdx.x == 0 && *sm.emax) atomicMax(emax, *sm.emax);
+  pass1_write(sm, n_items, s1, NT, orow, ocol, oval);
+}
+
 // ------------------------------------------------------------------------ pass 2
 // A bucket's pairs are cut into segments of SEG; segment ids run over all buckets
 // (segbase[b] is the first segment of bucket b, segbase[nb] their number).
@@ -754,9 +848,9 @@ __device__ __forceinline__ uint32_t slot_hash(uint32_t k) {
 // single-lane path for a sub-bucket whose distinct entries overflow the table: heap
 // sort the pairs in place by key, then exact sums of equal keys (same result as the
 // LDS path, which uses the same exact arithmetic).
-template <typename V>
+template <typename V, bool RES>
 __device__ void pass3_global(uint32_t* key, V* val, int64_t n, int64_t r0, int R, int colbits, int F, int32_t* tcol,
-                             V* tval, uint32_t* rowoff, uint32_t* usub) {
+                             V* tval, V* tres, uint32_t* rowoff, uint32_t* usub) {
   auto sift = [&](int64_t root, int64_t end) {
     while (true) {
       int64_t child = 2 * root + 1;
@@ -797,7 +891,9 @@ __device__ void pass3_global(uint32_t* key, V* val, int64_t n, int64_t r0, int R
       ++q;
     }
     tcol[u] = (int32_t)(k0 & cmask);
-    tval[u] = from_fixed_as<V>(lo, hi, F);
+    const V h = from_fixed_as<V>(lo, hi, F);
+    tval[u] = h;
+    if constexpr (RES) tres[u] = fixed_residual<V>(lo, hi, F, h);
     rowoff[r0 + (k0 >> colbits)] += 1;
     ++u;
   }
@@ -815,12 +911,13 @@ __device__ void pass3_global(uint32_t* key, V* val, int64_t n, int64_t r0, int R
 // sub-bucket) to rowoff, its total to usub[g].
 // Sub-buckets run in their natural order: under a random numbering the lower-triangle
 // pairs of a row grow with its id, so an even interleave keeps the XCDs balanced.
-template <typename V, int HT>
+// With RES, each entry's residual (the exact sum minus its rounding) goes to tres too.
+template <typename V, int HT, bool RES = false>
 __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* __restrict__ ival,
                                                const uint32_t* __restrict__ sbb, int s2, int colbits, int64_t n_node,
                                                const uint32_t* __restrict__ emax, int32_t* __restrict__ tcol,
-                                               V* __restrict__ tval, uint32_t* __restrict__ rowoff,
-                                               uint32_t* __restrict__ usub) {
+                                               V* __restrict__ tval, V* __restrict__ tres,
+                                               uint32_t* __restrict__ rowoff, uint32_t* __restrict__ usub) {
   constexpr int NT = 256, PER = 4;
   __shared__ uint32_t s_key[HT];
   __shared__ unsigned long long s_lo[HT];  // sum of low 48-bit chunks
@@ -911,7 +1008,8 @@ __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* _
   __syncthreads();
   if (s_over) {
     if (threadIdx.x == 0)
-      pass3_global<V>(ikey + beg, ival + beg, end - beg, r0, R, colbits, F, tcol + beg, tval + beg, rowoff, usub + g);
+      pass3_global<V, RES>(ikey + beg, ival + beg, end - beg, r0, R, colbits, F, tcol + beg, tval + beg,
+                           RES ? tres + beg : nullptr, rowoff, usub + g);
     return;
   }
   // order the U entries by (row, col): count per row, scan, group by row, rank by col
@@ -948,7 +1046,9 @@ __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* _
     tcol[beg + pos] = (int32_t)col;
     uint64_t lo, hi;
     join48(s_lo[h], (int64_t)s_hi[h], lo, hi);
-    tval[beg + pos] = from_fixed_as<V>(lo, hi, F);
+    const V hv = from_fixed_as<V>(lo, hi, F);
+    tval[beg + pos] = hv;
+    if constexpr (RES) tres[beg + pos] = fixed_residual<V>(lo, hi, F, hv);
   }
   for (int r = threadIdx.x; r < R; r += NT) rowoff[r0 + r] = s_ro[r];
   if (threadIdx.x == 0) usub[g] = U;
@@ -957,29 +1057,39 @@ __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* _
 // ------------------------------------------------------------------------- final
 // One wavefront per sub-bucket g: its entries copied to their final place ubase[g],
 // its rows' row_ptr = ubase[g] + local row offset.
-template <typename V>
+// GROUPED (running sums of a grouped build): also each entry's residual (tres -> res)
+// and its row (rows), the form in which the next group's pass reads them back.
+template <typename V, bool GROUPED = false>
 __global__ __launch_bounds__(256) void k_final(const uint32_t* __restrict__ sbb, const uint32_t* __restrict__ ubase,
                                                const int32_t* __restrict__ tcol, const V* __restrict__ tval,
-                                               const uint32_t* __restrict__ rowoff, int s2, int64_t n_node,
-                                               int64_t nsub, int32_t* __restrict__ row_ptr,
-                                               int32_t* __restrict__ col_idx, V* __restrict__ vals, int64_t cap,
+                                               const V* __restrict__ tres, const uint32_t* __restrict__ rowoff,
+                                               int s2, int64_t n_node, int64_t nsub, int32_t* __restrict__ row_ptr,
+                                               int32_t* __restrict__ col_idx, V* __restrict__ vals,
+                                               V* __restrict__ res, int32_t* __restrict__ rows, int64_t cap,
                                                uint32_t* __restrict__ status) {
   const int lane = threadIdx.x & 63;
   const int64_t g = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
   if (g >= nsub) return;
   const int64_t nnz = ubase[nsub];
   const uint32_t base = ubase[g], U = ubase[g + 1] - base;
+  const int64_t r0 = g << s2;
+  const int R = (int)min((int64_t)1 << s2, n_node - r0);
   if (nnz <= cap) {
     const uint32_t src = sbb[g];
     for (uint32_t f = lane; f < U; f += 64) {
       col_idx[base + f] = tcol[src + f];
       vals[base + f] = tval[src + f];
+      if constexpr (GROUPED) res[base + f] = tres[src + f];
+    }
+    if constexpr (GROUPED) {
+      for (int r = lane; r < R; r += 64) {
+        const uint32_t k1 = r + 1 < R ? rowoff[r0 + r + 1] : U;
+        for (uint32_t k = rowoff[r0 + r]; k < k1; ++k) rows[base + k] = (int32_t)(r0 + r);
+      }
     }
   } else if (g == 0 && lane == 0) {
     raise_flag(status, KB_F_CAPACITY);
   }
-  const int64_t r0 = g << s2;
-  const int R = (int)min((int64_t)1 << s2, n_node - r0);
   for (int r = lane; r < R; r += 64) row_ptr[r0 + r] = (int32_t)(base + rowoff[r0 + r]);
   if (g == nsub - 1 && lane == 0) row_ptr[n_node] = (int32_t)nnz;
 }

@@ -68,3 +68,6 @@ def sym_quad(row_ptr, col, val, u):
     v = np.asarray(val, np.float64)
     w = np.where(rows == col, 1.0, 2.0)
     return float(np.sum(w * v * u[rows] * u[col]))
+
+
+from meshgen import box_nnz  # noqa: E402,F401  (structured-box nnz, pinned in test_closed_forms)

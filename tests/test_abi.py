@@ -257,3 +257,52 @@ def test_assemble_dof_argument_errors():
         assert call(**{k: None}) == _lib.KB_EINVAL, k
     m.conn = None
     assert call() == _lib.KB_EINVAL
+
+
+def _plan_grouped(elem, nel, nn, group, cap, prec=1):
+    m = KbMesh(elem, 0, nel, nn, None, None, None)
+    ws = ctypes.c_size_t(0)
+    rc = _lib.lib().kb_plan_grouped(ctypes.byref(m), prec, None, group, cap, ctypes.byref(ws))
+    return rc, ws.value
+
+
+def test_plan_grouped():
+    # one group is the single pass
+    rc, ws1 = _plan_grouped(4, 1000, 300, 5000, 2000)
+    assert rc == 0 and ws1 >= _plan(4, 1000, 300, 1)[1]
+    # several groups carry the sums: workspace grows with the capacity
+    rc, wa = _plan_grouped(4, 1000, 300, 100, 2000)
+    rc2, wb = _plan_grouped(4, 1000, 300, 100, 4000)
+    assert rc == 0 and rc2 == 0 and wb > wa
+    assert _plan_grouped(4, 1000, 300, 0, 10)[0] == _lib.KB_EINVAL
+    assert _plan_grouped(4, 1000, 300, 10, -1)[0] == _lib.KB_EINVAL
+    # a pass's pairs: group * 10 + 2 * cap must stay below 2^31
+    assert _plan_grouped(4, 10 ** 9, 10 ** 6, 10 ** 8, 6 * 10 ** 8)[0] == _lib.KB_ERANGE
+
+
+def test_plan_grouped_beyond_one_pass():
+    """The Kuhn box 6 x 337^3: too many pairs for one pass, two groups fit."""
+    nel, nn, nnz = 6 * 337 ** 3, 338 ** 3, 307_546_875
+    assert _plan(4, nel, nn, 1)[0] == _lib.KB_ERANGE
+    rc, ws = _plan_grouped(4, nel, nn, (nel + 1) // 2, nnz)
+    assert rc == 0
+    assert ws < 80 * 2 ** 30  # well inside one GPU's memory
+
+
+def test_grouped_argument_errors():
+    L = _lib.lib()
+    m = KbMesh(4, 0, 1000, 300, 0x1000, 0x1000, 0x1000)
+    ws = ctypes.c_size_t(0)
+    assert L.kb_plan_grouped(ctypes.byref(m), 1, None, 100, 5000, ctypes.byref(ws)) == 0
+    f = ctypes.c_void_p(0x1000)
+
+    def call(**kw):
+        a = dict(g=100, ws=f, wsb=ws.value, rp=f, col=f, val=f, cap=5000, nnz=f, st=f)
+        a.update(kw)
+        return L.kb_build_lower_csr_grouped(ctypes.byref(m), 1, None, a["g"], a["ws"], a["wsb"], a["rp"], a["col"],
+                                            a["val"], a["cap"], a["nnz"], a["st"], None)
+
+    assert call(wsb=ws.value - 1) == _lib.KB_ENOSPC
+    assert call(g=0) == _lib.KB_EINVAL
+    for k in ("ws", "rp", "col", "val", "nnz", "st"):
+        assert call(**{k: None}) == _lib.KB_EINVAL, k
