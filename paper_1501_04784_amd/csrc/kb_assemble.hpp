@@ -918,7 +918,7 @@ __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* _
                                                const uint32_t* __restrict__ emax, int32_t* __restrict__ tcol,
                                                V* __restrict__ tval, V* __restrict__ tres,
                                                uint32_t* __restrict__ rowoff, uint32_t* __restrict__ usub) {
-  constexpr int NT = 256, PER = 4;
+  constexpr int NT = 256, PER = 8;
   __shared__ uint32_t s_key[HT];
   __shared__ unsigned long long s_lo[HT];  // sum of low 48-bit chunks
   __shared__ unsigned long long s_hi[HT];  // sum of signed high chunks
