@@ -160,7 +160,7 @@ int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p, int dof 
   // pass-1 tiles: pairs staged in LDS as (8-byte key, value).  Up to 8 rows: one
   // element per lane, `block` may pick the half-size tile (two workgroups per CU);
   // more rows (several DOFs per node): as many elements as keep the staged pairs near
-  // 110 KB, on 256 threads
+  // 110 KB, on kWideThreads threads
   if (p->nen <= 8) {
     const int big = p->nen == 4 ? (prec == KB_FP64 ? 768 : 1024) : (prec == KB_FP64 ? 192 : 256);
     const int small = big / 2 % 64 == 0 ? big / 2 : 64 * ((big / 2 + 63) / 64);
@@ -169,7 +169,7 @@ int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p, int dof 
     p->lds1 = (size_t)p->tile * p->te * (8 + p->vbytes) + 2 * 4 * (size_t)p->nb + 4 * (p->tile / 64 + 2);
   } else {
     p->tile = (int)std::min<size_t>(256, std::max<size_t>(1, kWideStage / ((size_t)p->te * (8 + p->vbytes))));
-    p->lds1 = (size_t)p->tile * p->te * (8 + p->vbytes) + 2 * 4 * (size_t)p->nb + 4 * (256 / 64 + 2) +
+    p->lds1 = (size_t)p->tile * p->te * (8 + p->vbytes) + 2 * 4 * (size_t)p->nb + 4 * (kWideThreads / 64 + 2) +
               (size_t)p->tile * p->nen * 12 + 4 * (size_t)p->tile + 2 * (size_t)p->te;
   }
   p->ntiles = div_up(p->nel, p->tile);
@@ -303,13 +303,13 @@ struct TileSizes {
   static constexpr int small = big / 2 >= 64 && (big / 2) % 64 == 0 ? big / 2 : 64 * ((big / 2 + 63) / 64);
 };
 
-// elements of more than 8 rows: `tile` elements on 256 threads, one tile per workgroup
+// elements of more than 8 rows: `tile` elements on kWideThreads threads, one tile per workgroup
 template <int NEN, typename V>
 int launch_pass1_wide(const Plan& p, const kb_mesh* m, const void* klow, unsigned char* ws, uint32_t* status,
                       hipStream_t s) {
   auto kern = k_pass1_wide<NEN, V>;
   if (!set_lds(kern, p.lds1)) return KB_EHIP;
-  kern<<<(unsigned)p.ntiles, 256, p.lds1, s>>>(m->conn, (const V*)klow, p.nel, p.nn, p.tile, p.s1, p.nb,
+  kern<<<(unsigned)p.ntiles, kWideThreads, p.lds1, s>>>(m->conn, (const V*)klow, p.nel, p.nn, p.tile, p.s1, p.nb,
                                               (const uint32_t*)(ws + p.o_hist), (uint16_t*)(ws + p.o_row1),
                                               (uint32_t*)(ws + p.o_col1), (V*)(ws + p.o_val1),
                                               (uint32_t*)(ws + p.o_emax), status);

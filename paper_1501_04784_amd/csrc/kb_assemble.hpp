@@ -532,20 +532,22 @@ __global__ __launch_bounds__(BLOCK) void k_pass1_tet(const int32_t* __restrict__
 
 // Elements of more than eight rows (nodes with several degrees of freedom), values
 // given (assembly only).  A tile is `te` elements, few enough that their pairs fit in
-// LDS; 256 threads work on it:
+// LDS; kWideThreads threads work on it:
 //   - per (element, row a): the row's rank r_a among the element's ids, and its run of
 //     r_a + 1 places in the tile's part of bucket E_a >> s1 (LDS counters);
 //   - per pair, one thread each, values read in storage order (coalesced): pair (p, q)
 //     belongs to the row of the larger id (a) and takes place rank(b) of that row's
 //     run, b being the other corner (the diagonal takes the last place, r_a);
 //   - the staged pairs, grouped by bucket, are written as runs (as for 4 and 8 rows).
+constexpr int kWideThreads = 1024;  // threads per wide pass-1 workgroup (one per CU: LDS)
+
 template <int NEN, typename V>
-__global__ __launch_bounds__(256) void k_pass1_wide(const int32_t* __restrict__ conn, const V* __restrict__ klow,
+__global__ __launch_bounds__(kWideThreads) void k_pass1_wide(const int32_t* __restrict__ conn, const V* __restrict__ klow,
                                                   int64_t n_elem, int64_t n_node, int te, int s1, int nb,
                                                   const uint32_t* __restrict__ off1, uint16_t* __restrict__ orow,
                                                   uint32_t* __restrict__ ocol, V* __restrict__ oval,
                                                   uint32_t* __restrict__ emax, uint32_t* __restrict__ status) {
-  constexpr int T = ElemTraits<NEN>::T, NT = 256;
+  constexpr int T = ElemTraits<NEN>::T, NT = kWideThreads;
   extern __shared__ __align__(16) unsigned char smem[];
   const Pass1Smem<V, NT> sm(smem, te * T, nb);
   int32_t* s_E = (int32_t*)(sm.emax + 1);    // [te * NEN] the tile's connectivity
