@@ -31,6 +31,7 @@ constexpr int kSegThreads = 512;   // threads per pass-2 scatter workgroup
 constexpr int kTargetBuckets = 256;  // first-level buckets (pass-1 run length)
 constexpr double kSubEntries = 300;   // target distinct entries per sub-bucket
 constexpr int kHTMin = 512, kHTMax = 4096;
+constexpr double kHalfTileRatio = 16;   // pairs per tile x bucket histogram entry
 constexpr size_t kWideStage = 112640;  // staged pair bytes per pass-1 tile, elements of > 8 rows
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -165,6 +166,13 @@ int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p, int dof 
     const int big = p->nen == 4 ? (prec == KB_FP64 ? 768 : 1024) : (prec == KB_FP64 ? 192 : 256);
     const int small = big / 2 % 64 == 0 ? big / 2 : 64 * ((big / 2 + 63) / 64);
     p->tile = big;
+    // bricks: the half tile (two workgroups per CU, one's gathers under the other's
+    // writes) when the tile x bucket histogram it doubles stays small next to the pairs
+    // (measured: randomly numbered 1M bricks 10% faster pass 1; the 256-brick batch, whose
+    // histogram is 1/6 of its pairs, 4% slower overall)
+    if (m->elem == KB_HEX8 && p->dof == 1 && p->nb > 0 &&
+        (double)p->T >= kHalfTileRatio * (double)p->nb * (double)div_up(p->nel, small))
+      p->tile = small;
     if (tu && (tu->block == big || tu->block == small)) p->tile = tu->block;
     p->lds1 = (size_t)p->tile * p->te * (8 + p->vbytes) + 2 * 4 * (size_t)p->nb + 4 * (p->tile / 64 + 2);
   } else {
