@@ -925,10 +925,10 @@ __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* _
   __shared__ unsigned long long s_lo[HT];  // sum of low 48-bit chunks
   __shared__ unsigned long long s_hi[HT];  // sum of signed high chunks
   __shared__ uint16_t s_slot[HT];  // occupied slots, in insertion order
+  __shared__ uint16_t s_wi[HT];    // each occupied slot's index within its row
   __shared__ uint32_t s_lcol[HT];  // columns of the occupied slots, grouped by row
   __shared__ uint32_t s_rc[256];   // entries per row
   __shared__ uint32_t s_ro[256];   // row offsets
-  __shared__ uint32_t s_scan[8];
   __shared__ uint32_t s_over, s_nu;
 
   const int64_t g = blockIdx.x;
@@ -980,8 +980,9 @@ __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* _
           while (true) {
             if (k == kEmptyKey) {
               k = atomicCAS(&s_key[h], kEmptyKey, key);
-              if (k == kEmptyKey) {  // inserted: record the slot
+              if (k == kEmptyKey) {  // inserted: record the slot and its place in its row
                 s_slot[atomicAdd(&s_nu, 1u)] = (uint16_t)h;
+                s_wi[h] = (uint16_t)atomicAdd(&s_rc[key >> colbits], 1u);
                 break;
               }
               if (k == key) break;
@@ -1014,27 +1015,38 @@ __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* _
                            RES ? tres + beg : nullptr, rowoff, usub + g);
     return;
   }
-  // order the U entries by (row, col): count per row, scan, group by row, rank by col
+  // order the U entries by (row, col): the row counts (taken at insertion) scanned by one
+  // wave, the entries grouped by row, then ranked by column within their row
   const uint32_t U = s_nu;
-  constexpr int KMAX = HT / NT;  // entries per thread at most
-  uint32_t wi[KMAX];             // each entry's index within its row
+  const int RB = 1 << s2;  // rows of a full sub-bucket (<= 256)
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    uint32_t v[4], sum = 0;
 #pragma unroll
-  for (int q = 0; q < KMAX; ++q) {
-    const uint32_t f = threadIdx.x + q * NT;
-    if (f < U) wi[q] = atomicAdd(&s_rc[s_key[s_slot[f]] >> colbits], 1u);
+    for (int k = 0; k < 4; ++k) {
+      const int r = lane * 4 + k;
+      v[k] = r < RB ? s_rc[r] : 0u;
+      sum += v[k];
+    }
+    uint32_t x = sum;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t y = __shfl_up(x, d, 64);
+      if (lane >= d) x += y;
+    }
+    uint32_t run = x - sum;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int r = lane * 4 + k;
+      if (r < RB) s_ro[r] = run;
+      run += v[k];
+    }
   }
   __syncthreads();
-  const int RB = 1 << s2;  // rows of a full sub-bucket (<= 256)
-  for (int r = threadIdx.x; r < RB; r += NT) s_ro[r] = s_rc[r];
-  __syncthreads();
-  block_scan_array(s_ro, RB, s_scan);
-#pragma unroll
-  for (int q = 0; q < KMAX; ++q) {
-    const uint32_t f = threadIdx.x + q * NT;
-    if (f < U) {
-      const uint32_t k = s_key[s_slot[f]];
-      s_lcol[s_ro[k >> colbits] + wi[q]] = k & cmask;
-    }
+  for (uint32_t f = threadIdx.x; f < U; f += NT) {
+    const uint32_t h = s_slot[f];
+    const uint32_t k = s_key[h];
+    s_lcol[s_ro[k >> colbits] + s_wi[h]] = k & cmask;
   }
   __syncthreads();
   for (uint32_t f = threadIdx.x; f < U; f += NT) {
