@@ -56,7 +56,7 @@ struct Plan {
   size_t lds1 = 0, lds2 = 0;
   // workspace offsets
   size_t o_coords4 = 0, o_hist = 0, o_histT = 0, o_part = 0, o_total = 0, o_bstart = 0, o_segbase = 0, o_hist2 = 0, o_seg2b = 0, o_emax = 0,
-         o_klow = 0, o_dconn = 0, o_tres = 0, o_row1 = 0, o_col1 = 0, o_val1 = 0, o_key2 = 0, o_val2 = 0, o_sbb = 0, o_rowoff = 0, o_usub = 0, o_ubase = 0,
+         o_dconn = 0, o_tres = 0, o_row1 = 0, o_col1 = 0, o_val1 = 0, o_key2 = 0, o_val2 = 0, o_sbb = 0, o_rowoff = 0, o_usub = 0, o_ubase = 0,
          total = 0;
 };
 
@@ -208,8 +208,6 @@ int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p, int dof 
   p->o_hist2 = take(4 * (size_t)(p->nseg_max * p->p2));
   p->o_seg2b = take(4 * (size_t)p->nseg_max);
   p->o_emax = take(4);
-  // mass builds integrate into element values first, then assemble them
-  p->o_klow = take(p->op == KB_OP_MASS && p->dof == 1 ? p->vbytes * T : 0);
   p->o_dconn = take(p->dof > 1 ? 4 * (size_t)p->nen * (size_t)p->nel : 0);  // expanded connectivity
   p->o_tres = take(csr_cap > 0 ? p->vbytes * T : 0);  // residuals of the reduced entries
   p->o_row1 = take(2 * T);
@@ -278,15 +276,15 @@ bool set_lds(K kernel, size_t bytes) {
          hipSuccess;
 }
 
-template <int NEN, Prec P, bool FROM_VALUES, int BLOCK>
+template <int NEN, Prec P, bool FROM_VALUES, int BLOCK, Op OP>
 int launch_pass1_block(const Plan& p, const kb_mesh* m, const void* klow, unsigned char* ws, uint32_t* status,
                        hipStream_t s) {
   using V = typename PrecTraits<P>::V;
   auto kern = [] {
     if constexpr (NEN == 4)
-      return k_pass1_tet<P, FROM_VALUES, BLOCK>;
+      return k_pass1_tet<P, FROM_VALUES, BLOCK, OP>;
     else
-      return k_pass1<NEN, P, FROM_VALUES, BLOCK>;
+      return k_pass1<NEN, P, FROM_VALUES, BLOCK, OP>;
   }();
   if (!set_lds(kern, p.lds1)) return KB_EHIP;
   // tetrahedra: persistent, the workgroups that fit on the device at once (LDS-bound),
@@ -325,7 +323,8 @@ int launch_pass1_wide(const Plan& p, const kb_mesh* m, const void* klow, unsigne
   return KB_OK;
 }
 
-template <int NEN, Prec P, bool FROM_VALUES>
+// OP: the integrand of pass 1 when the values are not given
+template <int NEN, Prec P, bool FROM_VALUES, Op OP = Op::Stiffness>
 int launch_pass1(const Plan& p, const kb_mesh* m, const void* klow, unsigned char* ws, uint32_t* status,
                  hipStream_t s) {
   if constexpr (NEN > 8) {
@@ -333,9 +332,9 @@ int launch_pass1(const Plan& p, const kb_mesh* m, const void* klow, unsigned cha
     return launch_pass1_wide<NEN, typename PrecTraits<P>::V>(p, m, klow, ws, status, s);
   } else {
     if (p.tile == TileSizes<NEN, P>::big)
-      return launch_pass1_block<NEN, P, FROM_VALUES, TileSizes<NEN, P>::big>(p, m, klow, ws, status, s);
+      return launch_pass1_block<NEN, P, FROM_VALUES, TileSizes<NEN, P>::big, OP>(p, m, klow, ws, status, s);
     if (p.tile == TileSizes<NEN, P>::small)
-      return launch_pass1_block<NEN, P, FROM_VALUES, TileSizes<NEN, P>::small>(p, m, klow, ws, status, s);
+      return launch_pass1_block<NEN, P, FROM_VALUES, TileSizes<NEN, P>::small, OP>(p, m, klow, ws, status, s);
     return KB_EINVAL;
   }
 }
@@ -494,29 +493,21 @@ int build_impl(const Plan& p, const kb_mesh* m, const void* klow, unsigned char*
     k_segments<<<1, 256, 0, s>>>(bstart, p.nb, p.seg, segbase);
     KB_LAUNCH_CHECK();
   }
-  if (p.ntiles > 0 && p.nb > 0 && !klow && p.op == KB_OP_STIFFNESS && p.nn > 0) {
+  if (p.ntiles > 0 && p.nb > 0 && !klow && p.nn > 0) {
     k_pad_coords<<<(unsigned)std::min<int64_t>(div_up(p.nn, 256), 8192), 256, 0, s>>>(m->coords, p.nn,
                                                                                      (double4*)(ws + p.o_coords4));
     KB_LAUNCH_CHECK();
   }
-  // the integrate stage is exactly one kernel (pass 1) for the stiffness matrix; a mass
-  // matrix is integrated into element values first and then assembled from them
+  // the integrate stage is exactly one kernel (pass 1), for either integrand
   KB_TRY(ev.rec(KB_STAGE_INTEGRATE));
-  if constexpr (NEN <= 8) {
-    if (!klow && p.op == KB_OP_MASS) {
-      if (p.nel > 0) {
-        k_integrate_store<NEN, P, Op::Mass><<<grid_for(p.nel, 256), 256, 0, s>>>(
-            m->conn, m->coords, m->coef, p.nel, p.nn, p.tau, (V*)(ws + p.o_klow), status);
-        KB_LAUNCH_CHECK();
-      }
-      klow = ws + p.o_klow;
-    }
-  }
   if (p.ntiles > 0 && p.nb > 0) {
     if (klow) {
       KB_TRY((launch_pass1<NEN, P, true>(p, m, klow, ws, status, s)));
     } else if constexpr (NEN <= 8) {
-      KB_TRY((launch_pass1<NEN, P, false>(p, m, nullptr, ws, status, s)));
+      if (p.op == KB_OP_MASS)
+        KB_TRY((launch_pass1<NEN, P, false, Op::Mass>(p, m, nullptr, ws, status, s)));
+      else
+        KB_TRY((launch_pass1<NEN, P, false>(p, m, nullptr, ws, status, s)));
     } else {
       return KB_EINVAL;  // several DOFs per node: values are always given
     }

@@ -390,8 +390,9 @@ __device__ __forceinline__ void read_values(const V* __restrict__ klow, int64_t 
 }
 
 // Bricks: one tile per workgroup; tiles are assigned XCD-contiguously, so the runs that
-// neighbouring tiles write side by side meet in one L2.
-template <int NEN, Prec P, bool FROM_VALUES, int BLOCK>
+// neighbouring tiles write side by side meet in one L2.  OP: the integrand (unless the
+// values are given).
+template <int NEN, Prec P, bool FROM_VALUES, int BLOCK, Op OP = Op::Stiffness>
 __global__ __launch_bounds__(BLOCK) void k_pass1(const int32_t* __restrict__ conn, const double4* __restrict__ coords4,
                                                const double* __restrict__ coef,
                                                const typename PrecTraits<P>::V* __restrict__ klow, int64_t n_elem,
@@ -427,7 +428,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass1(const int32_t* __restrict__ con
     if constexpr (FROM_VALUES)
       read_values<T>(klow, e, k, &flags);
     else
-      element_values<NEN, P>(NodesPadded{coords4}, coef, e, E, tau, k, &flags, &fb);
+      element_values<NEN, P, NodesPadded, OP>(NodesPadded{coords4}, coef, e, E, tau, k, &flags, &fb);
     atomicMax(sm.emax, values_emax<T>(k));
     pass1_stage<NEN>(sm, E, q, k, s1);
   }
@@ -442,7 +443,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass1(const int32_t* __restrict__ con
 // workgroups walk it interleaved (neighbouring runs again meet in one L2).  The next
 // tile's connectivity is loaded while the current tile is integrated, and its node
 // coordinates while the current tile is written.
-template <Prec P, bool FROM_VALUES, int BLOCK>
+template <Prec P, bool FROM_VALUES, int BLOCK, Op OP = Op::Stiffness>
 __global__ __launch_bounds__(BLOCK) void k_pass1_tet(const int32_t* __restrict__ conn,
                                                    const double4* __restrict__ coords4,
                                                    const double* __restrict__ coef,
@@ -503,7 +504,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass1_tet(const int32_t* __restrict__
       if constexpr (FROM_VALUES)
         read_values<T>(klow, e, k, &flags);
       else
-        element_values_at<NEN, P>(Xn, c_e, tau, k, &flags, &fb);
+        element_values_at<NEN, P, OP>(Xn, c_e, tau, k, &flags, &fb);
       const uint32_t me = values_emax<T>(k);
       em = me > em ? me : em;
       pass1_stage<NEN>(sm, E, q, k, s1);

@@ -239,7 +239,7 @@ __device__ __forceinline__ void gather_nodes(const NODES& nodes, const int32_t (
 
 // Integrate one element from its gathered node coordinates Xn and coefficient c into k
 // (value type V, c applied).  Adds flag bits to *f and counts a fallback in *fb.
-template <int NEN, Prec P>
+template <int NEN, Prec P, Op OP = Op::Stiffness>
 __device__ __forceinline__ void element_values_at(const double (&Xn)[NEN][3], double c, float tau,
                                                   typename PrecTraits<P>::V (&k)[ElemTraits<NEN>::T], uint32_t* f,
                                                   uint32_t* fb) {
@@ -252,7 +252,7 @@ __device__ __forceinline__ void element_values_at(const double (&Xn)[NEN][3], do
     for (int a = 0; a < NEN; ++a)
 #pragma unroll
       for (int j = 0; j < 3; ++j) X[a][j] = a ? Xn[a][j] - Xn[0][j] : 0.0;
-    ok = integrate<NEN, double, double, false>(X, k, 0.0, nullptr);
+    ok = integrate<NEN, double, double, false, OP>(X, k, 0.0, nullptr);
   } else {
     float X[NEN][3];
 #pragma unroll
@@ -260,7 +260,7 @@ __device__ __forceinline__ void element_values_at(const double (&Xn)[NEN][3], do
 #pragma unroll
       for (int j = 0; j < 3; ++j) X[a][j] = a ? (float)(Xn[a][j] - Xn[0][j]) : 0.f;
     bool need_fb = false;
-    ok = integrate<NEN, float, float, P == Prec::F32FB>(X, k, tau, &need_fb);
+    ok = integrate<NEN, float, float, P == Prec::F32FB, OP>(X, k, tau, &need_fb);
     if constexpr (P == Prec::F32FB) {
       if (need_fb) {
         // Jacobian, determinant and adjugate in FP64 for this element
@@ -269,7 +269,7 @@ __device__ __forceinline__ void element_values_at(const double (&Xn)[NEN][3], do
         for (int a = 0; a < NEN; ++a)
 #pragma unroll
           for (int j = 0; j < 3; ++j) Xd[a][j] = a ? Xn[a][j] - Xn[0][j] : 0.0;
-        ok = integrate<NEN, double, float, false>(Xd, k, 0.0, nullptr);
+        ok = integrate<NEN, double, float, false, OP>(Xd, k, 0.0, nullptr);
         *fb += 1;
       }
     }
