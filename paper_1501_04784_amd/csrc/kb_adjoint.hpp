@@ -12,9 +12,9 @@
 //
 // Node gradients are sums over the elements at each node.  They are accumulated as the
 // same exact fixed-point integers as the assembly (scale from the largest exponent of
-// all element contributions; two 64-bit integer atomics per value), so the result does
-// not depend on the order of the atomics: bitwise deterministic, exact while a node
-// belongs to at most 2^16 elements.
+// all element contributions; two 64-bit integer chunks per value, summed in LDS per
+// workgroup and then globally), so the result does not depend on the order of the
+// atomics: bitwise deterministic, exact while a node belongs to at most 2^16 elements.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -182,25 +182,61 @@ __global__ __launch_bounds__(128) void k_adjoint_elems(const int32_t* __restrict
   if (threadIdx.x == 0 && s_emax) atomicMax(emax, s_emax);
 }
 
-// Per (element, corner): its three coordinate gradients added to the node's exact
-// fixed-point accumulators acc[node][j] = (low chunk sum, high chunk sum).
+// Per workgroup, kScatEntries consecutive (element, corner) entries: their coordinate
+// gradients are summed per node in an LDS hash table (the same exact chunks, LDS
+// atomics), then each distinct node's sums are added once to its global fixed-point
+// accumulators acc[node][j] = (low chunk sum, high chunk sum).  Elements numbered with
+// locality share most of their nodes within a workgroup, so the global atomics (the
+// cost of this step) fall several fold; integer sums keep the result independent of
+// the order either way.
+constexpr int kScatEntries = 512, kScatSlots = 1024;  // at most half the slots in use
+
 template <int NEN>
 __global__ __launch_bounds__(256) void k_adjoint_scatter(const int32_t* __restrict__ conn, int64_t n_elem,
                                                          int64_t n_node, const double* __restrict__ gel,
                                                          const uint32_t* __restrict__ emax,
                                                          unsigned long long* __restrict__ acc) {
+  __shared__ int32_t s_node[kScatSlots];
+  __shared__ unsigned long long s_acc[kScatSlots][6];
   const int F = 1117 - (int)*emax;
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n_elem * NEN;
-       t += (int64_t)gridDim.x * blockDim.x) {
+  for (int h = threadIdx.x; h < kScatSlots; h += blockDim.x) {
+    s_node[h] = -1;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) s_acc[h][c] = 0ull;
+  }
+  __syncthreads();
+  const int64_t n = n_elem * NEN;
+  const int64_t t0 = (int64_t)blockIdx.x * kScatEntries;
+  for (int64_t t = t0 + threadIdx.x; t < t0 + kScatEntries && t < n; t += blockDim.x) {
     const int32_t node = conn[t];
     if (node < 0 || node >= n_node) continue;  // its element was flagged and contributes zeros
+    uint32_t h = ((uint32_t)node * 2654435769u) >> (32 - 10);  // kScatSlots = 2^10
+    while (true) {  // at most kScatEntries keys in kScatSlots slots: a free slot exists
+      const int32_t k = s_node[h];
+      if (k == node) break;
+      if (k == -1) {
+        const int32_t prev = atomicCAS(&s_node[h], -1, node);
+        if (prev == -1 || prev == node) break;
+      }
+      h = (h + 1) & (kScatSlots - 1);
+    }
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
       uint64_t c0;
       int64_t c1;
       to_chunks(gel[t * 3 + j], F, c0, c1);
-      if (c0) atomicAdd(&acc[((int64_t)node * 3 + j) * 2], (unsigned long long)c0);
-      if (c1) atomicAdd(&acc[((int64_t)node * 3 + j) * 2 + 1], (unsigned long long)c1);
+      if (c0) atomicAdd(&s_acc[h][2 * j], (unsigned long long)c0);
+      if (c1) atomicAdd(&s_acc[h][2 * j + 1], (unsigned long long)c1);
+    }
+  }
+  __syncthreads();
+  for (int h = threadIdx.x; h < kScatSlots; h += blockDim.x) {
+    const int32_t node = s_node[h];
+    if (node < 0) continue;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const unsigned long long v = s_acc[h][c];
+      if (v) atomicAdd(&acc[(int64_t)node * 6 + c], v);
     }
   }
 }

@@ -960,7 +960,7 @@ int kb_adjoint_lower(const kb_mesh* mesh, const int32_t* row_ptr, const int32_t*
       k_adjoint_elems<4><<<ge, 128, 0, s>>>(mesh->conn, mesh->coords, mesh->coef, nel, nn, row_ptr, col_idx, w,
                                             grad_coef, gel, emax, status_dev);
     KB_LAUNCH_CHECK();
-    const unsigned gs = (unsigned)std::min<int64_t>(div_up(nel * nen, 256), 65536);
+    const unsigned gs = (unsigned)div_up(nel * nen, kScatEntries);
     if (nen == 8)
       k_adjoint_scatter<8><<<gs, 256, 0, s>>>(mesh->conn, nel, nn, gel, emax, acc);
     else
