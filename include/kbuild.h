@@ -33,11 +33,12 @@
  *                 has an estimated infinity-norm condition number above tau gets its
  *                 Jacobian, determinant and inverse in FP64 (float).
  *
- * Memory and streams.  Every pointer passed to kb_build_lower_csr,
- * kb_integrate_lower and kb_assemble_lower_csr is a device pointer (except the
- * kb_mesh / kb_tuning structs themselves, which are host memory read during the
- * call).  The caller owns and allocates all memory; the library allocates nothing
- * and keeps no state between calls.  Work is enqueued on `stream` (a hipStream_t)
+ * Memory and streams.  Every array passed to the kb_build / kb_integrate /
+ * kb_assemble / kb_adjoint calls is a device pointer (except the kb_mesh, kb_batch
+ * and kb_tuning structs themselves, which are host memory read during the call).
+ * The caller owns and allocates all memory; the library allocates nothing and keeps
+ * no state between calls apart from a per-device cache of the compute-unit count
+ * (read once with hipDeviceGetAttribute).  Work is enqueued on `stream` (a hipStream_t)
  * and the calls return without synchronising; results are valid once the stream
  * reaches that point.  Calls that share a workspace must be ordered on one stream.
  * The output of a call is bitwise deterministic for given inputs and precision.
@@ -115,10 +116,11 @@ typedef struct {
 
 /* Optional tuning knobs; pass NULL for defaults.  Zero fields mean "default". */
 typedef struct {
-  int32_t block;           /* threads per workgroup of kb_integrate_lower (64..1024); if
-                              it equals the default element tile of the build or half
-                              of it (tet4: 1024 / 512, FP64 768 / 384; hex8: 256 / 128,
-                              FP64 192 / 128) it also sets that tile                    */
+  int32_t block;           /* threads per workgroup of kb_integrate_lower (64..1024,
+                              at most 256 used); if it equals one of the build's two
+                              element tiles (tet4: 1024 / 512, FP64 768 / 384; hex8:
+                              256 / 128, FP64 192 / 128) it also sets that tile, which
+                              the build otherwise picks from the mesh shape          */
   int32_t bucket_bits;     /* log2 rows per first-level bucket, <= 16 (0 = from mesh shape) */
   float fb_tau;            /* KB_FP32_FB64 condition-number threshold (> 1)             */
   int32_t sub_bits;        /* log2 rows per sub-bucket, <= bucket_bits and <= 8 (0 = auto) */
