@@ -728,7 +728,23 @@ __global__ __launch_bounds__(256) void k_hist2(const uint16_t* __restrict__ irow
   const uint32_t be = bstart[b + 1];
   const uint32_t i0 = bstart[b] + s * SEG, i1 = (i0 + SEG < be) ? i0 + SEG : be;
   const uint32_t mask = (uint32_t)p2 - 1;
-  for (uint32_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) atomicAdd(&s_h[(irow[i] >> s2) & mask], 1u);
+  // four row indices per 8-byte load over the 4-aligned middle of the range (irow is
+  // 256-byte aligned); the ragged ends one by one
+  const uint32_t a0 = (i0 + 3u) & ~3u, a1 = i1 & ~3u;
+  if (a0 >= a1) {
+    for (uint32_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) atomicAdd(&s_h[(irow[i] >> s2) & mask], 1u);
+  } else {
+    for (uint32_t i = i0 + threadIdx.x; i < a0; i += blockDim.x) atomicAdd(&s_h[(irow[i] >> s2) & mask], 1u);
+    for (uint32_t i = a1 + threadIdx.x; i < i1; i += blockDim.x) atomicAdd(&s_h[(irow[i] >> s2) & mask], 1u);
+    const uint2* __restrict__ w = (const uint2*)(irow + a0);
+    for (uint32_t j = threadIdx.x; j < (a1 - a0) / 4; j += blockDim.x) {
+      const uint2 v = w[j];
+      atomicAdd(&s_h[((v.x & 0xFFFFu) >> s2) & mask], 1u);
+      atomicAdd(&s_h[((v.x >> 16) >> s2) & mask], 1u);
+      atomicAdd(&s_h[((v.y & 0xFFFFu) >> s2) & mask], 1u);
+      atomicAdd(&s_h[((v.y >> 16) >> s2) & mask], 1u);
+    }
+  }
   __syncthreads();
   for (int j = threadIdx.x; j < p2; j += blockDim.x) hist2[(int64_t)sid * p2 + j] = s_h[j];
 }
