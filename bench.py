@@ -309,8 +309,8 @@ class MeshTotals:
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU design is described "
-              "in DESIGN.md but not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU design is "
+              "documented but not built", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
