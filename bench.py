@@ -372,10 +372,13 @@ def main():
         dom = max(SINGLE_KERNEL_STAGES, key=lambda k: stages[k])
         kernel = SINGLE_KERNEL_STAGES[dom] + ("_tet" if dom == "integrate" and m.elem == 4 else "")
         achieved = ab[dom] / (stages[dom] * 1e-3) / 1e9
+        traffic = stored_traffic(kernel, args.workload, prec)
         out["roofline"] = {"bound": "hbm", "kernel": kernel, "stage": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                           "traffic": stored_traffic(kernel, args.workload, prec),
-                           "kernel_ms": stages[dom], "algorithmic_bytes": ab[dom]}
+                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                           "kernel_ms": stages[dom], "algorithmic_bytes": ab[dom],
+                           # measured bytes per launch over this run's kernel time: how busy the
+                           # memory system is, wasted bytes (partly used lines) included
+                           "traffic_frac": (traffic / (stages[dom] * 1e-3) / 1e9 / HBM_PEAK_GBS) if traffic else None}
         out["stages_ms"] = stages
     if not args.no_fp64 and prec != "fp64":
         ms64, _, st64, r64 = time_builds(kb, torch, mesh_dev, m, "fp64", max(3, args.steps // 2), 2,
