@@ -180,12 +180,13 @@ CONFIG_NAMES = {
     4: "batch of 256 hex8 boxes, cells per axis U{8..64}, h=1/64, jitter 0.2h, c log-U[1e-2,1e2]",
     5: "hex8 box 64^3, jitter 0.2h, c log-U[1e-1,1e1], FP64 (+ seeded normal loss weights)",
     6: "tet4 Kuhn 6x337^3, jitter 0.2h, c log-U[1e-3,1e3] (more element pairs than one pass indexes)",
+    7: "hex8 unit cube 300^3, undistorted, c=1 (the largest mesh of Table 2)",
 }
-CONFIG_FULL_N = {1: 10, 2: 100, 3: 150, 5: 64, 6: 337}
+CONFIG_FULL_N = {1: 10, 2: 100, 3: 150, 5: 64, 6: 337, 7: 300}
 
 
 def config_mesh(cid: int, n: int | None = None) -> Mesh:
-    """Mesh of workload ``cid`` (1, 2, 3, 5 or 6); ``n`` shrinks the cube for tests."""
+    """Mesh of workload ``cid`` (1, 2, 3, 5, 6 or 7); ``n`` shrinks the cube for tests."""
     n = CONFIG_FULL_N[cid] if n is None else n
     if cid == 1:
         return box_mesh(8, n, jitter=0.2, coef=1.0, seed=1)
@@ -197,6 +198,8 @@ def config_mesh(cid: int, n: int | None = None) -> Mesh:
         return box_mesh(8, n, jitter=0.2, coef=(1e-1, 1e1), seed=5)
     if cid == 6:
         return box_mesh(4, n, jitter=0.2, coef=(1e-3, 1e3), seed=7)
+    if cid == 7:
+        return box_mesh(8, n, jitter=0.0, coef=1.0, seed=0)
     raise ValueError(f"config {cid} is not a single mesh")
 
 

@@ -1,6 +1,6 @@
 """The single-mesh workloads at full size, in the launch configuration the benchmark
-times (default tuning, its precision): the Kuhn tet box 6 x 150^3 (20,250,000 elements)
-and the brick box 100^3 (1,000,000 elements).
+times (default tuning, its precision): the Kuhn tet box 6 x 150^3 (20,250,000 elements),
+the brick box 100^3 (1,000,000 elements) and the 300^3 brick cube of Table 2.
 
 * the pattern: nnz against the closed form of the box, columns ascending within each
   row, the diagonal last and positive;
@@ -117,3 +117,15 @@ def test_brick_100_full_size():
     rows, col = check_pattern(m, r, (100, 100, 100))
     check_row_sums(r, rows, col, "fp32fb64")
     check_sampled_rows(m, r, "fp32fb64")
+
+
+def test_brick_300_table2_full_size():
+    """The largest mesh of the paper's Table 2 (27,000,000 undistorted unit-cube bricks,
+    27,270,901 nodes), FP64 as the paper's values: nnz, rows against the oracle, row sums."""
+    m = workload(7)
+    say(f"[full] hex 300^3 fp64 nel={m.n_elem} nn={m.n_node}")
+    r = kb.build_lower_csr(*to_dev(m), m.elem, prec="fp64")
+    rows, col = check_pattern(m, r, (300, 300, 300))
+    check_row_sums(r, rows, col, "fp64")
+    del rows, col
+    check_sampled_rows(m, r, "fp64", n_sample=800)
