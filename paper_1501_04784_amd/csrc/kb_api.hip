@@ -55,7 +55,7 @@ struct Plan {
   int64_t csr_cap = 0, ntiles_csr = 0;  // running sums read back as pairs (grouped builds)
   size_t lds1 = 0, lds2 = 0;
   // workspace offsets
-  size_t o_coords4 = 0, o_hist = 0, o_histT = 0, o_part = 0, o_total = 0, o_bstart = 0, o_segbase = 0, o_hist2 = 0, o_seg2b = 0, o_emax = 0,
+  size_t o_coords4 = 0, o_hist = 0, o_csum = 0, o_tot = 0, o_part = 0, o_total = 0, o_bstart = 0, o_segbase = 0, o_hist2 = 0, o_seg2b = 0, o_emax = 0,
          o_dconn = 0, o_tres = 0, o_row1 = 0, o_col1 = 0, o_val1 = 0, o_key2 = 0, o_val2 = 0, o_sbb = 0, o_rowoff = 0, o_usub = 0, o_ubase = 0,
          total = 0;
 };
@@ -196,11 +196,12 @@ int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p, int dof 
     return o;
   };
   const size_t T = (size_t)p->T;
-  const int64_t scan_n = std::max(p->nhist, p->nsub + 1);
+  const int64_t scan_n = std::max<int64_t>(p->nb, p->nsub + 1);
   p->o_coords4 = take(p->dof > 1 ? 0 : 32 * (size_t)p->nn);  // assembly with several DOFs: no geometry
   // scan outputs hold n + 1 words: the scan writes its total after the last entry
   p->o_hist = take(4 * (size_t)p->nhist);
-  p->o_histT = take(4 * ((size_t)p->nhist + 1));
+  p->o_csum = take(4 * (size_t)div_up(p->ntiles + p->ntiles_csr, kColChunk) * (size_t)p->nb);
+  p->o_tot = take(4 * (size_t)p->nb);
   p->o_part = take(4 * (size_t)(div_up(scan_n, kScanChunk) + 1));
   p->o_total = take(8);
   p->o_bstart = take(4 * ((size_t)p->nb + 1));
@@ -258,14 +259,6 @@ int scan(const int32_t* in, int64_t n, int32_t* part, int32_t* out, int64_t* tot
   k_scan_top<<<1, kScanThreads, 0, s>>>(part, nb);
   KB_LAUNCH_CHECK();
   k_scan_down<<<(unsigned)nb, kScanThreads, 0, s>>>(in, n, part, out, total64);
-  KB_LAUNCH_CHECK();
-  return KB_OK;
-}
-
-int transpose(const uint32_t* in, uint32_t* out, int64_t rows, int64_t cols, hipStream_t s) {
-  if (rows == 0 || cols == 0) return KB_OK;
-  dim3 g((unsigned)div_up(cols, 32), (unsigned)div_up(rows, 32));
-  k_transpose<<<g, 256, 0, s>>>(in, out, rows, cols);
   KB_LAUNCH_CHECK();
   return KB_OK;
 }
@@ -453,7 +446,8 @@ int build_impl(const Plan& p, const kb_mesh* m, const void* klow, unsigned char*
                hipStream_t s, const Carry* cr = nullptr) {
   using V = typename PrecTraits<P>::V;
   auto* hist = (uint32_t*)(ws + p.o_hist);
-  auto* histT = (uint32_t*)(ws + p.o_histT);
+  auto* csum = (uint32_t*)(ws + p.o_csum);
+  auto* tot = (uint32_t*)(ws + p.o_tot);
   auto* part = (int32_t*)(ws + p.o_part);
   auto* total = (int64_t*)(ws + p.o_total);
   auto* bstart = (uint32_t*)(ws + p.o_bstart);
@@ -485,11 +479,21 @@ int build_impl(const Plan& p, const kb_mesh* m, const void* klow, unsigned char*
   }
   KB_TRY(ev.rec(KB_STAGE_OFFSETS));
   if (p.nb > 0) {
-    KB_TRY(transpose(hist, histT, nt_all, p.nb, s));  // -> [nb][tiles]
-    KB_TRY(scan((const int32_t*)histT, p.nb * nt_all, part, (int32_t*)histT, total, s));
-    k_bucket_starts<<<grid_for(p.nb + 1, 256), 256, 0, s>>>(histT, nt_all, p.nb, total, bstart);
+    // tile offsets: column sums per chunk of tiles, their scan per bucket, bucket starts,
+    // then the offsets in place (the histogram stays tile-major)
+    const int64_t nchunk = div_up(nt_all, kColChunk);
+    const dim3 gc((unsigned)nchunk, (unsigned)div_up(p.nb, 256));
+    if (nchunk > 0) {
+      k_col_chunks<<<gc, 256, 0, s>>>(hist, nt_all, p.nb, csum);
+      KB_LAUNCH_CHECK();
+    }
+    k_col_scan<<<(unsigned)p.nb, 256, 0, s>>>(csum, nchunk, p.nb, tot);
     KB_LAUNCH_CHECK();
-    KB_TRY(transpose(histT, hist, p.nb, nt_all, s));  // -> [tiles][nb]
+    KB_TRY(scan((const int32_t*)tot, p.nb, part, (int32_t*)bstart, total, s));
+    if (nchunk > 0) {
+      k_col_offsets<<<gc, 256, 0, s>>>(hist, csum, bstart, nt_all, p.nb);
+      KB_LAUNCH_CHECK();
+    }
     k_segments<<<1, 256, 0, s>>>(bstart, p.nb, p.seg, segbase);
     KB_LAUNCH_CHECK();
   }

@@ -253,29 +253,57 @@ __global__ __launch_bounds__(256) void k_hist_buckets(const int32_t* __restrict_
   for (int b = threadIdx.x; b < nb; b += blockDim.x) hist[t * nb + b] = s_h[b];
 }
 
-// out[c][r] = in[r][c] for an (rows x cols) uint32 matrix
-__global__ __launch_bounds__(256) void k_transpose(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
-                                                   int64_t rows, int64_t cols) {
-  __shared__ uint32_t tile[32][33];
-  const int64_t c0 = (int64_t)blockIdx.x * 32, r0 = (int64_t)blockIdx.y * 32;
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
-  for (int k = ty; k < 32; k += 8) {
-    const int64_t r = r0 + k, c = c0 + tx;
-    tile[k][tx] = (r < rows && c < cols) ? in[r * cols + c] : 0u;
-  }
-  __syncthreads();
-  for (int k = ty; k < 32; k += 8) {
-    const int64_t c = c0 + k, r = r0 + tx;
-    if (c < cols && r < rows) out[c * rows + r] = tile[tx][k];
-  }
+// Tile offsets from the tile-major histogram hist[t][b] (tiles x buckets) without
+// transposing it: column sums over chunks of kColChunk tiles, a scan of those per bucket,
+// then each chunk's columns walked again, counts turned into offsets in place:
+// hist[t][b] = bstart[b] + (pairs of bucket b in tiles before t).
+constexpr int kColChunk = 64;
+
+// grid (chunks, ceil(nb / 256)): csum[c][b] = sum of hist[t][b] over the tiles of chunk c
+__global__ __launch_bounds__(256) void k_col_chunks(const uint32_t* __restrict__ hist, int64_t ntiles, int nb,
+                                                    uint32_t* __restrict__ csum) {
+  const int64_t c = blockIdx.x;
+  const int b = blockIdx.y * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  const int64_t t0 = c * kColChunk, t1 = t0 + kColChunk < ntiles ? t0 + kColChunk : ntiles;
+  uint32_t sum = 0;
+#pragma unroll 8
+  for (int64_t t = t0; t < t1; ++t) sum += hist[t * nb + b];
+  csum[c * nb + b] = sum;
 }
 
-// bucket b starts at offT[b * ntiles] (bucket-major scanned histogram); bstart[nb] = total
-__global__ void k_bucket_starts(const uint32_t* __restrict__ offT, int64_t ntiles, int nb, const int64_t* total,
-                                uint32_t* __restrict__ bstart) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b < nb) bstart[b] = ntiles > 0 ? offT[(int64_t)b * ntiles] : 0u;
-  if (b == nb) bstart[nb] = (uint32_t)*total;
+// one workgroup per bucket b: exclusive scan of csum[.][b] over the chunks, in place; the
+// bucket's total to tot[b]
+__global__ __launch_bounds__(256) void k_col_scan(uint32_t* __restrict__ csum, int64_t nchunk, int nb,
+                                                  uint32_t* __restrict__ tot) {
+  __shared__ uint32_t s_scan[8];
+  const int b = blockIdx.x;
+  uint32_t carry = 0;
+  for (int64_t c0 = 0; c0 < nchunk; c0 += blockDim.x) {
+    const int64_t c = c0 + threadIdx.x;
+    const uint32_t v = c < nchunk ? csum[c * nb + b] : 0u;
+    uint32_t total;
+    const uint32_t ex = block_scan_u32(v, s_scan, &total);
+    if (c < nchunk) csum[c * nb + b] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0) tot[b] = carry;
+}
+
+// grid (chunks, ceil(nb / 256)): counts of chunk c turned into offsets in place
+__global__ __launch_bounds__(256) void k_col_offsets(uint32_t* __restrict__ hist, const uint32_t* __restrict__ csum,
+                                                     const uint32_t* __restrict__ bstart, int64_t ntiles, int nb) {
+  const int64_t c = blockIdx.x;
+  const int b = blockIdx.y * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  uint32_t run = bstart[b] + csum[c * nb + b];
+  const int64_t t0 = c * kColChunk, t1 = t0 + kColChunk < ntiles ? t0 + kColChunk : ntiles;
+#pragma unroll 8
+  for (int64_t t = t0; t < t1; ++t) {
+    const uint32_t v = hist[t * nb + b];
+    hist[t * nb + b] = run;
+    run += v;
+  }
 }
 
 // single block: segbase[b] = number of pass-2 segments in buckets before b
