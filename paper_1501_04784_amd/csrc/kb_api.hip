@@ -174,7 +174,8 @@ int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p, int dof 
         (double)p->T >= kHalfTileRatio * (double)p->nb * (double)div_up(p->nel, small))
       p->tile = small;
     if (tu && (tu->block == big || tu->block == small)) p->tile = tu->block;
-    p->lds1 = (size_t)p->tile * p->te * (8 + p->vbytes) + 2 * 4 * (size_t)p->nb + 4 * (p->tile / 64 + 2);
+    // (scan words for up to two lanes per element)
+    p->lds1 = (size_t)p->tile * p->te * (8 + p->vbytes) + 2 * 4 * (size_t)p->nb + 4 * (2 * p->tile / 64 + 2);
   } else {
     p->tile = (int)std::min<size_t>(256, std::max<size_t>(1, kWideStage / ((size_t)p->te * (8 + p->vbytes))));
     p->lds1 = (size_t)p->tile * p->te * (8 + p->vbytes) + 2 * 4 * (size_t)p->nb + 4 * (kWideThreads / 64 + 2) +
@@ -273,6 +274,18 @@ template <int NEN, Prec P, bool FROM_VALUES, int BLOCK, Op OP>
 int launch_pass1_block(const Plan& p, const kb_mesh* m, const void* klow, unsigned char* ws, uint32_t* status,
                        hipStream_t s) {
   using V = typename PrecTraits<P>::V;
+  if constexpr (NEN == 8 && !FROM_VALUES && OP == Op::Stiffness && P != Prec::F64) {
+    // bricks in FP32: a lane pair per element, 2 * BLOCK lanes for a tile of BLOCK elements
+    // (in FP64 the pair kernel sits at the register limit and was slower on 1M bricks)
+    auto kern = k_pass1_pair<P, 2 * BLOCK>;
+    if (!set_lds(kern, p.lds1)) return KB_EHIP;
+    kern<<<(unsigned)p.ntiles, 2 * BLOCK, p.lds1, s>>>(m->conn, (const double4*)(ws + p.o_coords4), m->coef, p.nel,
+                                                       p.nn, p.tau, p.s1, p.nb, (const uint32_t*)(ws + p.o_hist),
+                                                       (uint16_t*)(ws + p.o_row1), (uint32_t*)(ws + p.o_col1),
+                                                       (V*)(ws + p.o_val1), (uint32_t*)(ws + p.o_emax), status);
+    KB_LAUNCH_CHECK();
+    return KB_OK;
+  }
   auto kern = [] {
     if constexpr (NEN == 4)
       return k_pass1_tet<P, FROM_VALUES, BLOCK, OP>;

@@ -467,6 +467,90 @@ __global__ __launch_bounds__(BLOCK) void k_pass1(const int32_t* __restrict__ con
   pass1_write(sm, n_items, s1, BLOCK, orow, ocol, oval);
 }
 
+// stage the pairs of rows R0 .. R0+3 of a brick (the lane's half of a lane pair)
+template <int R0, typename V, typename SM>
+__device__ __forceinline__ void pair_stage_half(const SM& sm, const int32_t (&E)[8], const uint32_t (&q)[4],
+                                                const V (&k)[36], int s1) {
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int row = R0 + a;
+    uint32_t pos = sm.cnt[E[row] >> s1] + q[a];
+    const uint64_t rk = (uint64_t)(uint32_t)E[row] << 32;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      if (E[b] <= E[row]) {
+        sm.key[pos] = rk | (uint32_t)E[b];
+        sm.val[pos] = row >= b ? k[lidx(row, b)] : k[lidx(b, row)];
+        ++pos;
+      }
+    }
+  }
+}
+
+// Bricks, stiffness matrix: a lane pair per element (element_values_pair), BLOCK lanes
+// and BLOCK / 2 elements per tile.  Twice the waves of one lane per element for the same
+// staging LDS, and half the quadrature per lane; lane h counts and stages the pairs of
+// rows 4h .. 4h+3.
+template <Prec P, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_pass1_pair(const int32_t* __restrict__ conn,
+                                                    const double4* __restrict__ coords4,
+                                                    const double* __restrict__ coef, int64_t n_elem, int64_t n_node,
+                                                    float tau, int s1, int nb, const uint32_t* __restrict__ off1,
+                                                    uint16_t* __restrict__ orow, uint32_t* __restrict__ ocol,
+                                                    typename PrecTraits<P>::V* __restrict__ oval,
+                                                    uint32_t* __restrict__ emax, uint32_t* __restrict__ status) {
+  using V = typename PrecTraits<P>::V;
+  constexpr int NEN = 8, T = ElemTraits<NEN>::T, TE = BLOCK / 2;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const Pass1Smem<V, BLOCK> sm(smem, TE * T, nb);
+  const int64_t t = xcd_item(blockIdx.x, gridDim.x);
+  for (int b = threadIdx.x; b < nb; b += BLOCK) {
+    sm.cnt[b] = 0;
+    sm.base[b] = off1[t * nb + b];
+  }
+  if (threadIdx.x == 0) *sm.emax = 0;
+  __syncthreads();
+  const int h = (int)(threadIdx.x & 1);
+  const int64_t e = t * TE + (threadIdx.x >> 1);
+  int32_t E[NEN];
+  bool valid = false;
+  if (e < n_elem) {
+    load_conn<NEN>(conn, e, E);
+    valid = check_conn<NEN>(E, n_node) == 0;
+  }
+  // offsets of the lane's four rows in their buckets (a branch per half keeps every
+  // index into E and r a constant)
+  uint32_t q[4];
+  if (valid) {
+    int r[NEN];
+    node_ranks<NEN>(E, r);
+    if (h) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) q[a] = atomicAdd(&sm.cnt[E[4 + a] >> s1], (uint32_t)(r[4 + a] + 1));
+    } else {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) q[a] = atomicAdd(&sm.cnt[E[a] >> s1], (uint32_t)(r[a] + 1));
+    }
+  }
+  __syncthreads();
+  const uint32_t n_items = block_scan_array(sm.cnt, nb, sm.scan);
+  uint32_t flags = 0, fb = 0;
+  if (valid) {
+    V k[T];
+    element_values_pair<P>(NodesPadded{coords4}, coef, e, E, tau, h, k, &flags, &fb);
+    atomicMax(sm.emax, values_emax<T>(k));
+    if (h)
+      pair_stage_half<4>(sm, E, q, k, s1);
+    else
+      pair_stage_half<0>(sm, E, q, k, s1);
+  }
+  if (flags) raise_flag(status, flags);
+  if (fb) atomicAdd(&status[1], fb);
+  __syncthreads();
+  if (threadIdx.x == 0 && *sm.emax) atomicMax(emax, *sm.emax);
+  pass1_write(sm, n_items, s1, BLOCK, orow, ocol, oval);
+}
+
 // Tetrahedra: persistent workgroups.  XCD x owns one contiguous range of tiles and its
 // workgroups walk it interleaved (neighbouring runs again meet in one L2).  The next
 // tile's connectivity is loaded while the current tile is integrated, and its node

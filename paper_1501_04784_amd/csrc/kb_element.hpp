@@ -135,6 +135,59 @@ __device__ __forceinline__ bool hex_integrate(const GT (&X)[8][3], AT (&k)[36], 
   return ok;
 }
 
+// Half of the 2x2x2 rule, for two lanes sharing one brick: the four points with r = -g
+// (h = 0) or r = +g (h = 1).  The same arithmetic per point as hex_integrate; the
+// derivatives of the lane's half are picked once per point from the two constants.
+template <typename GT, typename AT, bool CHECK>
+__device__ __forceinline__ bool hex_integrate_half(const GT (&X)[8][3], AT (&k)[36], GT tau, bool* need_fb, int h) {
+  bool ok = true;
+#pragma unroll
+  for (int p = 0; p < 36; ++p) k[p] = AT(0);
+#pragma unroll
+  for (int qq = 0; qq < 4; ++qq) {
+    GT dN[3][8];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int a = 0; a < 8; ++a) dN[i][a] = h ? GT(hex_dN(4 + qq, i, a)) : GT(hex_dN(qq, i, a));
+    GT J[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        GT s = GT(0);
+#pragma unroll
+        for (int a = 1; a < 8; ++a) s += dN[i][a] * X[a][j];
+        J[i][j] = s;
+      }
+    GT A[3][3];
+    const GT det = adjugate(J, A);
+    ok = ok && (det > GT(0));
+    if (CHECK) {
+      if (ill_conditioned(J, A, det, tau)) *need_fb = true;
+    }
+    AT G[3][8];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        AT s = AT(0);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) s += AT(A[i][j]) * AT(dN[j][a]);
+        G[i][a] = s;
+      }
+    const AT f = AT(GT(1) / det);
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const AT g0 = f * G[0][a], g1 = f * G[1][a], g2 = f * G[2][a];
+#pragma unroll
+      for (int b = 0; b <= a; ++b) k[lidx(a, b)] += g0 * G[0][b] + g1 * G[1][b] + g2 * G[2][b];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  return ok;
+}
+
 // ---- tetrahedron: J rows are the edge vectors from node 0 (dN constant) -------------
 // X[a][j] = x_j(node a) - x_j(node 0), a = 1..3.  One point, weight 1/6.
 template <typename GT, typename AT, bool CHECK>

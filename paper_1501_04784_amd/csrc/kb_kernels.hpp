@@ -347,6 +347,73 @@ __device__ __forceinline__ void element_values(const NODES& nodes, const double*
   if (!finite) *f |= KB_F_NONFINITE;
 }
 
+// A brick integrated by a lane pair (lanes 2i and 2i+1; h = lane & 1): lane h gathers
+// nodes 4h .. 4h+3, the coordinates relative to node 0 are exchanged by shuffles, each
+// lane integrates the four points of its half of the rule and the two halves of k are
+// added.  Both lanes of a pair must be active together; both end with the same k and
+// flags (the fallback is counted once, by h = 0).
+template <Prec P>
+__device__ __forceinline__ void element_values_pair(const NodesPadded& nodes, const double* __restrict__ coef,
+                                                    int64_t e, const int32_t (&E)[8], float tau, int h,
+                                                    typename PrecTraits<P>::V (&k)[36], uint32_t* f, uint32_t* fb) {
+  using V = typename PrecTraits<P>::V;
+  double xo[4][3];  // (a branch per half keeps every index into E a constant)
+  if (h) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a) nodes.get(E[4 + a], xo[a]);
+  } else {
+#pragma unroll
+    for (int a = 0; a < 4; ++a) nodes.get(E[a], xo[a]);
+  }
+  double X0[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const double other = __shfl_xor(xo[0][j], 1, 64);
+    X0[j] = h ? other : xo[0][j];
+  }
+  double Xd[8][3];  // all eight nodes relative to node 0: own half and the partner's
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const double mine = xo[a][j] - X0[j];
+      const double other = __shfl_xor(mine, 1, 64);
+      Xd[a][j] = h ? other : mine;
+      Xd[4 + a][j] = h ? mine : other;
+    }
+  const double c = coef[e];
+  bool ok;
+  if constexpr (P == Prec::F64) {
+    ok = hex_integrate_half<double, double, false>(Xd, k, 0.0, nullptr, h);
+  } else {
+    float X[8][3];
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) X[a][j] = (float)Xd[a][j];
+    bool need_fb = false;
+    ok = hex_integrate_half<float, float, P == Prec::F32FB>(X, k, tau, &need_fb, h);
+    if constexpr (P == Prec::F32FB) {
+      need_fb = need_fb || (__shfl_xor((int)need_fb, 1, 64) != 0);
+      if (need_fb) {  // the whole element, both halves, with FP64 geometry
+        ok = hex_integrate_half<double, float, false>(Xd, k, 0.0, nullptr, h);
+        if (h == 0) *fb += 1;
+      }
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < 36; ++p) k[p] += __shfl_xor(k[p], 1, 64);
+  ok = ok && (__shfl_xor((int)ok, 1, 64) != 0);
+  bool finite = true;
+#pragma unroll
+  for (int p = 0; p < 36; ++p) {
+    k[p] = (V)(c * (double)k[p]);
+    finite = finite && isfinite((double)k[p]);
+  }
+  if (!ok) *f |= KB_F_INVERTED;
+  if (!finite) *f |= KB_F_NONFINITE;
+}
+
 template <int NEN, Prec P, Op OP = Op::Stiffness>
 __global__ __launch_bounds__(256) void k_integrate_store(const int32_t* __restrict__ conn,
                                                          const double* __restrict__ coords,
