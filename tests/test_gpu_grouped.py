@@ -129,3 +129,14 @@ def test_grouped_beyond_one_pass():
     check_row_sums(r, rows, col, "fp32fb64")
     del rows, col
     check_sampled_rows(m, r, "fp32fb64", n_sample=400)
+
+
+def test_grouped_heavy_row_takes_the_fallback_path():
+    """A star of 20,000 tets around one node whose id is the largest: its row gathers
+    80,000 pairs, more than a sub-bucket's table holds, so each pass sums it on the
+    reduce kernel's single-lane path, with residuals carried between the groups."""
+    from tests.test_gpu_parity import _fan
+
+    m = _fan(20000, center_last=True, seed=3)
+    compare_to_single(m, "fp64", 6000)
+    compare_to_single(m, "fp32fb64", 6000)
