@@ -968,12 +968,18 @@ __global__ __launch_bounds__(NT) void k_scatter2(const uint16_t* __restrict__ ir
 }
 
 // ------------------------------------------------------------------------ pass 3
-// home slot of a packed key in a table of HT (a power of two) slots: multiplicative
-// (Fibonacci) hashing, the top bits of key * 2^32/phi
+// home slot of a packed key in a table of HT (a power of two) slots: the top bits of
+// the key mixed by xor-shift, multiply by 2^32/phi, xor-shift.  A plain multiplicative
+// hash lets the row bits (the key's top bits) and the columns of a naturally numbered
+// grid interfere: on the 300^3 brick box it gave 1.9 probes per insert on average and
+// runs of up to 15, against 1.1 and 4 for the mixed key (the reduce 1.9x slower)
 template <int HT>
 __device__ __forceinline__ uint32_t slot_hash(uint32_t k) {
   constexpr int bits = __builtin_ctz(HT);
-  return (k * 0x9E3779B1u) >> (32 - bits);
+  k ^= k >> 15;
+  k *= 0x9E3779B1u;
+  k ^= k >> 13;
+  return k >> (32 - bits);
 }
 
 // single-lane path for a sub-bucket whose distinct entries overflow the table: heap
