@@ -1056,15 +1056,20 @@ __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* _
                                                V* __restrict__ tval, V* __restrict__ tres,
                                                uint32_t* __restrict__ rowoff, uint32_t* __restrict__ usub) {
   constexpr int NT = 256, PER = 8;
+  // once summed, each slot's value (and residual) is kept in place of its low chunk sum,
+  // which frees the high chunk sums for the columns grouped by row (one array fewer, six
+  // workgroups per CU at 1024 slots); a double with its double residual needs both words
+  constexpr bool kSepCols = RES && sizeof(V) == 8;
   __shared__ uint32_t s_key[HT];
-  __shared__ unsigned long long s_lo[HT];  // sum of low 48-bit chunks
-  __shared__ unsigned long long s_hi[HT];  // sum of signed high chunks
+  __shared__ unsigned long long s_lo[HT];  // sum of low 48-bit chunks, then value (+ residual)
+  __shared__ unsigned long long s_hi[HT];  // sum of signed high chunks, then the columns
   __shared__ uint16_t s_slot[HT];  // occupied slots, in insertion order
   __shared__ uint16_t s_wi[HT];    // each occupied slot's index within its row
-  __shared__ uint32_t s_lcol[HT];  // columns of the occupied slots, grouped by row
+  __shared__ uint32_t s_sep[kSepCols ? HT : 1];
   __shared__ uint32_t s_rc[256];   // entries per row
   __shared__ uint32_t s_ro[256];   // row offsets
   __shared__ uint32_t s_over, s_nu;
+  uint32_t* const s_lcol = kSepCols ? s_sep : (uint32_t*)s_hi;  // columns of the slots, grouped by row
 
   const int64_t g = blockIdx.x;
   const uint32_t beg = sbb[g], end = sbb[g + 1];
@@ -1151,9 +1156,23 @@ __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* _
     return;
   }
   // order the U entries by (row, col): the row counts (taken at insertion) scanned by one
-  // wave, the entries grouped by row, then ranked by column within their row
+  // wave while the others round each sum to its value, the entries grouped by row, then
+  // ranked by column within their row
   const uint32_t U = s_nu;
   const int RB = 1 << s2;  // rows of a full sub-bucket (<= 256)
+  for (uint32_t f = threadIdx.x < 64 ? U : threadIdx.x - 64; f < U; f += NT - 64) {
+    const uint32_t h = s_slot[f];
+    uint64_t lo, hi;
+    join48(s_lo[h], (int64_t)s_hi[h], lo, hi);
+    const V hv = from_fixed_as<V>(lo, hi, F);
+    if constexpr (sizeof(V) == 8) {
+      s_lo[h] = (unsigned long long)__double_as_longlong((double)hv);
+      if constexpr (RES) s_hi[h] = (unsigned long long)__double_as_longlong((double)fixed_residual<V>(lo, hi, F, hv));
+    } else {
+      const uint32_t rv = RES ? __float_as_uint((float)fixed_residual<V>(lo, hi, F, hv)) : 0u;
+      s_lo[h] = ((unsigned long long)rv << 32) | __float_as_uint((float)hv);
+    }
+  }
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x;
     uint32_t v[4], sum = 0;
@@ -1193,11 +1212,14 @@ __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* _
     for (uint32_t q = 0; q < nr; ++q) rank += (s_lcol[ro + q] < col) ? 1u : 0u;
     const uint32_t pos = ro + rank;
     tcol[beg + pos] = (int32_t)col;
-    uint64_t lo, hi;
-    join48(s_lo[h], (int64_t)s_hi[h], lo, hi);
-    const V hv = from_fixed_as<V>(lo, hi, F);
-    tval[beg + pos] = hv;
-    if constexpr (RES) tres[beg + pos] = fixed_residual<V>(lo, hi, F, hv);
+    const unsigned long long w = s_lo[h];
+    if constexpr (sizeof(V) == 8) {
+      tval[beg + pos] = (V)__longlong_as_double((long long)w);
+      if constexpr (RES) tres[beg + pos] = (V)__longlong_as_double((long long)s_hi[h]);
+    } else {
+      tval[beg + pos] = (V)__uint_as_float((uint32_t)w);
+      if constexpr (RES) tres[beg + pos] = (V)__uint_as_float((uint32_t)(w >> 32));
+    }
   }
   for (int r = threadIdx.x; r < R; r += NT) rowoff[r0 + r] = s_ro[r];
   if (threadIdx.x == 0) usub[g] = U;
