@@ -131,6 +131,40 @@ def test_bitwise_determinism(prec):
         assert x.tobytes() == y.tobytes()
 
 
+def renumbered(m, seed):
+    """The same mesh with its nodes renumbered and its elements reordered (each element's
+    local node order kept): old node i becomes p[i]."""
+    rng = np.random.default_rng(seed)
+    p = rng.permutation(m.n_node).astype(np.int64)
+    q = rng.permutation(m.n_elem)
+    coords = np.empty_like(m.coords)
+    coords[p] = m.coords
+    return meshgen.Mesh(m.elem, p[m.conn[q]].astype(np.int32), coords, m.coef[q]), p
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("elem,dims", [(8, (23, 17, 11)), (4, (13, 11, 9)), (8, (60, 60, 60))])
+def test_renumbering_permutes_k_bitwise(elem, dims, prec):
+    """Every element value is computed from the same coordinates in the same local order
+    and each entry is an exact sum rounded once, so renumbering the nodes of a naturally
+    numbered box (and reordering its elements) must permute K bit for bit: entry (i, j)
+    moves to (max(p_i, p_j), min(p_i, p_j)), K being symmetric."""
+    m = meshgen.box_mesh(elem, *dims, jitter=0.2, coef=(0.1, 10), seed=31)
+    mp, p = renumbered(m, 32)
+    say(f"[renumber] elem={elem} dims={dims} {prec} nel={m.n_elem}")
+    n = m.n_node
+    rp, col, _ = np_csr(r0 := gpu_build(m, prec))
+    rq, colq, _ = np_csr(r1 := gpu_build(mp, prec))
+    val, valq = r0.vals.cpu().numpy(), r1.vals.cpu().numpy()
+    a = p[np.repeat(np.arange(n), np.diff(rp))]
+    b = p[col.astype(np.int64)]
+    key_old = np.maximum(a, b) * n + np.minimum(a, b)
+    key_new = np.repeat(np.arange(n, dtype=np.int64), np.diff(rq)) * n + colq.astype(np.int64)
+    o, w = np.argsort(key_old, kind="stable"), np.argsort(key_new, kind="stable")
+    np.testing.assert_array_equal(key_old[o], key_new[w])
+    assert val[o].tobytes() == valq[w].tobytes()
+
+
 def test_empty_mesh():
     m = meshgen.Mesh(4, np.zeros((0, 4), np.int32), np.zeros((5, 3)), np.zeros(0))
     conn, coords, coef = to_dev(m)
