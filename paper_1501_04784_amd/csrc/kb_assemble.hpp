@@ -826,6 +826,25 @@ __global__ __launch_bounds__(256) void k_seg_map(const uint32_t* __restrict__ se
 }
 
 // histogram of sub-buckets ((row >> s2) mod p2) per segment: hist2[s * p2 + j]
+// s[k] += 1 for each of N keys, one LDS atomic per run of equal consecutive keys (under a
+// natural numbering neighbouring pairs mostly share a sub-bucket, and their increments
+// would otherwise serialise on one address: 27M bricks, histogram 2.26 -> 1.01 ms)
+template <int N>
+__device__ __forceinline__ void count_runs(uint32_t* s, const uint32_t (&k)[N]) {
+  uint32_t cur = k[0], run = 1;
+#pragma unroll
+  for (int i = 1; i < N; ++i) {
+    if (k[i] == cur) {
+      ++run;
+    } else {
+      atomicAdd(&s[cur], run);
+      cur = k[i];
+      run = 1;
+    }
+  }
+  atomicAdd(&s[cur], run);
+}
+
 template <int SEG>
 __global__ __launch_bounds__(256) void k_hist2(const uint16_t* __restrict__ irow, const uint32_t* __restrict__ bstart,
                                                const uint32_t* __restrict__ segbase,
@@ -840,21 +859,22 @@ __global__ __launch_bounds__(256) void k_hist2(const uint16_t* __restrict__ irow
   const uint32_t be = bstart[b + 1];
   const uint32_t i0 = bstart[b] + s * SEG, i1 = (i0 + SEG < be) ? i0 + SEG : be;
   const uint32_t mask = (uint32_t)p2 - 1;
-  // four row indices per 8-byte load over the 4-aligned middle of the range (irow is
+  // eight row indices per 16-byte load over the 8-aligned middle of the range (irow is
   // 256-byte aligned); the ragged ends one by one
-  const uint32_t a0 = (i0 + 3u) & ~3u, a1 = i1 & ~3u;
+  const uint32_t a0 = (i0 + 7u) & ~7u, a1 = i1 & ~7u;
   if (a0 >= a1) {
     for (uint32_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) atomicAdd(&s_h[(irow[i] >> s2) & mask], 1u);
   } else {
     for (uint32_t i = i0 + threadIdx.x; i < a0; i += blockDim.x) atomicAdd(&s_h[(irow[i] >> s2) & mask], 1u);
     for (uint32_t i = a1 + threadIdx.x; i < i1; i += blockDim.x) atomicAdd(&s_h[(irow[i] >> s2) & mask], 1u);
-    const uint2* __restrict__ w = (const uint2*)(irow + a0);
-    for (uint32_t j = threadIdx.x; j < (a1 - a0) / 4; j += blockDim.x) {
-      const uint2 v = w[j];
-      atomicAdd(&s_h[((v.x & 0xFFFFu) >> s2) & mask], 1u);
-      atomicAdd(&s_h[((v.x >> 16) >> s2) & mask], 1u);
-      atomicAdd(&s_h[((v.y & 0xFFFFu) >> s2) & mask], 1u);
-      atomicAdd(&s_h[((v.y >> 16) >> s2) & mask], 1u);
+    const uint4* __restrict__ w = (const uint4*)(irow + a0);
+    for (uint32_t j = threadIdx.x; j < (a1 - a0) / 8; j += blockDim.x) {
+      const uint4 v = w[j];
+      const uint32_t k[8] = {((v.x & 0xFFFFu) >> s2) & mask, ((v.x >> 16) >> s2) & mask,
+                             ((v.y & 0xFFFFu) >> s2) & mask, ((v.y >> 16) >> s2) & mask,
+                             ((v.z & 0xFFFFu) >> s2) & mask, ((v.z >> 16) >> s2) & mask,
+                             ((v.w & 0xFFFFu) >> s2) & mask, ((v.w >> 16) >> s2) & mask};
+      count_runs<8>(s_h, k);
     }
   }
   __syncthreads();
