@@ -225,6 +225,29 @@ __device__ __forceinline__ V fixed_residual(uint64_t lo, uint64_t hi, int F, V h
 // ---------------------------------------------------------------------- histogram
 // Per tile of `te` elements: pairs per bucket (row >> s1), written tile-major
 // hist[t * nb + b].  Flags index errors; invalid elements contribute nothing.
+// Reserve the pairs of local rows OFF .. OFF+N-1 of an element in their buckets' LDS
+// counters: each run of consecutive rows in one bucket takes one atomic for its total
+// (under a natural numbering an element's neighbouring nodes mostly share a bucket, and
+// per-row increments from neighbouring lanes would serialise on one address); a row
+// after the first of its run starts where its predecessor's pairs end.  q: first place
+// of each row's r+1 pairs within the bucket's part of the tile.
+template <int N, int OFF, int NE>
+__device__ __forceinline__ void reserve_rows(uint32_t* cnt, const int32_t (&E)[NE], const int (&r)[NE], int s1,
+                                             uint32_t (&q)[N]) {
+  uint32_t tot[N];  // pairs from row a to the end of its run
+  tot[N - 1] = (uint32_t)(r[OFF + N - 1] + 1);
+#pragma unroll
+  for (int a = N - 2; a >= 0; --a)
+    tot[a] = (uint32_t)(r[OFF + a] + 1) + ((E[OFF + a] >> s1) == (E[OFF + a + 1] >> s1) ? tot[a + 1] : 0u);
+#pragma unroll
+  for (int a = 0; a < N; ++a) {
+    if (a > 0 && (E[OFF + a] >> s1) == (E[OFF + a - 1] >> s1))
+      q[a] = q[a - 1] + (uint32_t)(r[OFF + a - 1] + 1);
+    else
+      q[a] = atomicAdd(&cnt[E[OFF + a] >> s1], tot[a]);
+  }
+}
+
 template <int NEN>
 __global__ __launch_bounds__(256) void k_hist_buckets(const int32_t* __restrict__ conn, int64_t n_elem, int64_t n_node,
                                                       int te, int s1, int nb, uint32_t* __restrict__ hist,
@@ -245,8 +268,8 @@ __global__ __launch_bounds__(256) void k_hist_buckets(const int32_t* __restrict_
     }
     int r[NEN];
     node_ranks<NEN>(E, r);
-#pragma unroll
-    for (int a = 0; a < NEN; ++a) atomicAdd(&s_h[E[a] >> s1], (uint32_t)(r[a] + 1));
+    uint32_t q[NEN];
+    reserve_rows<NEN, 0>(s_h, E, r, s1, q);
   }
   if (flags) raise_flag(status, flags);
   __syncthreads();
@@ -350,10 +373,7 @@ struct Pass1Smem {
 template <int NEN, typename SM>
 __device__ __forceinline__ uint32_t pass1_count(const SM& sm, const int32_t (&E)[NEN], const int (&r)[NEN], bool valid,
                                                 int s1, int nb, uint32_t (&q)[NEN]) {
-  if (valid) {
-#pragma unroll
-    for (int a = 0; a < NEN; ++a) q[a] = atomicAdd(&sm.cnt[E[a] >> s1], (uint32_t)(r[a] + 1));
-  }
+  if (valid) reserve_rows<NEN, 0>(sm.cnt, E, r, s1, q);
   __syncthreads();
   return block_scan_array(sm.cnt, nb, sm.scan);
 }
