@@ -117,10 +117,12 @@ typedef struct {
 /* Optional tuning knobs; pass NULL for defaults.  Zero fields mean "default". */
 typedef struct {
   int32_t block;           /* threads per workgroup of kb_integrate_lower (64..1024,
-                              at most 256 used); if it equals one of the build's two
+                              at most 256 used); if it equals one of the build's
                               element tiles (tet4: 1024 / 512, FP64 768 / 384; hex8:
-                              256 / 128, FP64 192 / 128) it also sets that tile, which
-                              the build otherwise picks from the mesh shape          */
+                              256 / 128, FP64 256 / 192 / 128) it also sets that tile,
+                              which the build otherwise picks from the mesh shape
+                              (FP64 hex8 256 needs at most about 2000 row buckets:
+                              beyond, 192 is taken instead)                          */
   int32_t bucket_bits;     /* log2 rows per first-level bucket, <= 16 (0 = from mesh shape) */
   float fb_tau;            /* KB_FP32_FB64 condition-number threshold (> 1)             */
   int32_t sub_bits;        /* log2 rows per sub-bucket, <= bucket_bits and <= 8 (0 = auto) */

@@ -163,8 +163,16 @@ int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p, int dof 
   // more rows (several DOFs per node): as many elements as keep the staged pairs near
   // 110 KB, on kWideThreads threads
   if (p->nen <= 8) {
-    const int big = p->nen == 4 ? (prec == KB_FP64 ? 768 : 1024) : (prec == KB_FP64 ? 192 : 256);
+    const int big = p->nen == 4 ? (prec == KB_FP64 ? 768 : 1024) : 256;
     const int small = big / 2 % 64 == 0 ? big / 2 : 64 * ((big / 2 + 63) / 64);
+    // FP64 with 8 rows: the 256 tile's staged pairs take 147 KB; with more than about
+    // 2000 buckets their counters no longer fit beside it, and a 192 tile takes over
+    // (measured on the 27M bricks, FP64: 256 lanes, one wave on each SIMD, pass 1
+    // 12.2 -> 9.5 ms against 192)
+    const int mid = (p->nen == 8 && prec == KB_FP64) ? 192 : 0;
+    auto lds_of = [&](int tile) {  // (scan words for up to two lanes per element)
+      return (size_t)tile * p->te * (8 + p->vbytes) + 2 * 4 * (size_t)p->nb + 4 * (2 * (size_t)tile / 64 + 2);
+    };
     p->tile = big;
     // bricks: the half tile (two workgroups per CU, one's gathers under the other's
     // writes) when the tile x bucket histogram it doubles stays small next to the pairs
@@ -173,9 +181,9 @@ int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p, int dof 
     if (m->elem == KB_HEX8 && p->dof == 1 && p->nb > 0 &&
         (double)p->T >= kHalfTileRatio * (double)p->nb * (double)div_up(p->nel, small))
       p->tile = small;
-    if (tu && (tu->block == big || tu->block == small)) p->tile = tu->block;
-    // (scan words for up to two lanes per element)
-    p->lds1 = (size_t)p->tile * p->te * (8 + p->vbytes) + 2 * 4 * (size_t)p->nb + 4 * (2 * p->tile / 64 + 2);
+    if (tu && (tu->block == big || tu->block == small || (mid && tu->block == mid))) p->tile = tu->block;
+    if (mid && p->tile == big && lds_of(big) > 163840) p->tile = mid;
+    p->lds1 = lds_of(p->tile);
   } else {
     p->tile = (int)std::min<size_t>(256, std::max<size_t>(1, kWideStage / ((size_t)p->te * (8 + p->vbytes))));
     p->lds1 = (size_t)p->tile * p->te * (8 + p->vbytes) + 2 * 4 * (size_t)p->nb + 4 * (kWideThreads / 64 + 2) +
@@ -311,7 +319,8 @@ int launch_pass1_block(const Plan& p, const kb_mesh* m, const void* klow, unsign
 // value size; the staging LDS is tile * pairs * (8 + value bytes)
 template <int NEN, Prec P>
 struct TileSizes {
-  static constexpr int big = NEN == 4 ? (P == Prec::F64 ? 768 : 1024) : (P == Prec::F64 ? 192 : 256);
+  static constexpr int big = NEN == 4 ? (P == Prec::F64 ? 768 : 1024) : 256;
+  static constexpr int mid = NEN == 8 && P == Prec::F64 ? 192 : 0;  // FP64, many buckets
   static constexpr int small = big / 2 >= 64 && (big / 2) % 64 == 0 ? big / 2 : 64 * ((big / 2 + 63) / 64);
 };
 
@@ -341,6 +350,10 @@ int launch_pass1(const Plan& p, const kb_mesh* m, const void* klow, unsigned cha
       return launch_pass1_block<NEN, P, FROM_VALUES, TileSizes<NEN, P>::big, OP>(p, m, klow, ws, status, s);
     if (p.tile == TileSizes<NEN, P>::small)
       return launch_pass1_block<NEN, P, FROM_VALUES, TileSizes<NEN, P>::small, OP>(p, m, klow, ws, status, s);
+    if constexpr (TileSizes<NEN, P>::mid > 0) {
+      if (p.tile == TileSizes<NEN, P>::mid)
+        return launch_pass1_block<NEN, P, FROM_VALUES, TileSizes<NEN, P>::mid, OP>(p, m, klow, ws, status, s);
+    }
     return KB_EINVAL;
   }
 }

@@ -73,6 +73,18 @@ def test_plan_sizes(elem, te, prec):
     assert ws % 256 == 0
 
 
+def test_plan_fp64_brick_tile_falls_back_with_many_buckets():
+    """FP64 bricks stage 256 elements per pass-1 tile unless their bucket counters no
+    longer fit beside them in LDS (beyond about 2000 buckets); then the 192 tile, also when
+    256 is asked for.  The tile shows in the workspace (one histogram row per tile)."""
+    def t(b):
+        return KbTuning(b, 0, 0.0, 0, None)
+    few = [_plan(8, 10000, 60_000_000, 0, tuning=t(b)) for b in (0, 256, 192)]  # 1831 buckets
+    assert all(r[0] == 0 for r in few) and few[0][1] == few[1][1] != few[2][1]
+    many = [_plan(8, 10000, 80_000_000, 0, tuning=t(b)) for b in (0, 256, 192)]  # 4883 buckets
+    assert all(r[0] == 0 for r in many) and many[0][1] == many[1][1] == many[2][1]
+
+
 def test_plan_empty_mesh():
     rc, ws, nt = _plan(4, 0, 0)
     assert rc == 0 and nt == 0
