@@ -72,6 +72,25 @@ def test_build_parity(name, prec):
     assert err <= TOL[prec]
 
 
+@pytest.mark.parametrize("op", ["stiffness", "mass"])
+@pytest.mark.parametrize("block", [256, 192, 128])
+def test_fp64_brick_tiles(block, op):
+    """Every FP64 brick pass-1 tile (256 by default, 192 where many buckets crowd the LDS,
+    128 the half tile), forced through the tuning, against the oracle: a randomly numbered
+    box spanning several tiles with a ragged last one."""
+    m = meshgen.box_mesh(8, 23, 19, 11, jitter=0.25, coef=(0.1, 10), permute_nodes=True, permute_elems=True,
+                         seed=77)
+    say(f"[tile] block={block} {op} nel={m.n_elem}")
+    conn, coords, coef = to_dev(m)
+    r = kb.build_lower_csr(conn, coords, coef, 8, prec="fp64", op=op, tuning=kb.Tuning(block=block))
+    rp, col, val = np_csr(r)
+    orp, ocol, oval, oflags = (oracle.build_mass_mesh if op == "mass" else oracle.build_mesh)(m)
+    assert oflags == 0 and r.flags == 0
+    np.testing.assert_array_equal(rp, orp)
+    np.testing.assert_array_equal(col, ocol)
+    assert scaled_error(orp, ocol, val, oval) <= TOL["fp64"]
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32fb64"])
 @pytest.mark.parametrize("elem,n", [(8, 40), (4, 30)])
 def test_build_parity_medium(elem, n, prec):
