@@ -321,27 +321,52 @@ def integrate_lower(conn, coords, coef, elem: int, prec="fp64", tuning: Tuning |
 
 
 # ---- adjoint ---------------------------------------------------------------------------
+class AdjointBuilder:
+    """Reusable adjoint context for one mesh shape: workspace, gradients and status are
+    allocated once, and ``run`` only enqueues kernels on the current stream."""
+
+    def __init__(self, elem: int, n_elem: int, n_node: int, device="cuda"):
+        self.elem, self.n_elem, self.n_node = int(elem), int(n_elem), int(n_node)
+        m = _mesh(self.elem, self.n_elem, self.n_node)
+        ws_bytes = ctypes.c_size_t(0)
+        _check(_lib.lib().kb_plan_adjoint(ctypes.byref(m), ctypes.byref(ws_bytes)), "kb_plan_adjoint")
+        self.ws_bytes = int(ws_bytes.value)
+        dev = torch.device(device)
+        self.ws = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=dev)
+        self.grad_coef = torch.empty(self.n_elem, dtype=torch.float64, device=dev)
+        self.grad_coords = torch.empty((self.n_node, 3), dtype=torch.float64, device=dev)
+        self.status = torch.zeros(KB_STATUS_WORDS, dtype=torch.int32, device=dev)
+
+    def run(self, conn, coords, coef, row_ptr, col_idx, w):
+        """Enqueue dL/dc and dL/dX of L = sum w_ij K_ij (w float64, one per pattern entry)."""
+        _validate_mesh(conn, coords, coef, self.elem)
+        if conn.shape[0] != self.n_elem or coords.shape[0] != self.n_node:
+            raise ValueError("mesh shape differs from the one this context was made for")
+        if w.dtype != torch.float64 or w.numel() != col_idx.numel() or not w.is_contiguous():
+            raise ValueError("w must be a contiguous float64 tensor with one weight per pattern entry")
+        m = _mesh(self.elem, self.n_elem, self.n_node, conn, coords, coef)
+        rc = _lib.lib().kb_adjoint_lower(ctypes.byref(m), _ptr(row_ptr), _ptr(col_idx), _ptr(w), _ptr(self.ws),
+                                         self.ws_bytes, _ptr(self.grad_coef), _ptr(self.grad_coords),
+                                         _ptr(self.status), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        _check(rc, "kb_adjoint_lower")
+
+    def result(self, check: bool = True, allow_flags: int = 0):
+        """Synchronise and return (dL/dc, dL/dX); raise on data errors if ``check``."""
+        torch.cuda.current_stream().synchronize()
+        if check:
+            _raise_on_flags(int(self.status[0].item()) & 0xFFFFFFFF, allow_flags)
+        return self.grad_coef, self.grad_coords
+
+
 def adjoint_lower(conn, coords, coef, elem: int, row_ptr, col_idx, w, check=True, allow_flags: int = 0):
     """(dL/dc [n_elem], dL/dX [n_node, 3]) of L = sum w_ij K_ij over the lower pattern
     (row_ptr, col_idx) of this mesh's K, w (float64) aligned with that pattern.  FP64."""
     _validate_mesh(conn, coords, coef, elem)
-    if w.dtype != torch.float64 or w.numel() != col_idx.numel() or not w.is_contiguous():
-        raise ValueError("w must be a contiguous float64 tensor with one weight per pattern entry")
-    m = _mesh(elem, conn.shape[0], coords.shape[0], conn, coords, coef)
-    L = _lib.lib()
-    ws_bytes = ctypes.c_size_t(0)
-    _check(L.kb_plan_adjoint(ctypes.byref(m), ctypes.byref(ws_bytes)), "kb_plan_adjoint")
-    ws = torch.empty(max(int(ws_bytes.value), 1), dtype=torch.uint8, device=conn.device)
-    gc = torch.empty(conn.shape[0], dtype=torch.float64, device=conn.device)
-    gx = torch.empty((coords.shape[0], 3), dtype=torch.float64, device=conn.device)
-    status = torch.zeros(KB_STATUS_WORDS, dtype=torch.int32, device=conn.device)
-    rc = L.kb_adjoint_lower(ctypes.byref(m), _ptr(row_ptr), _ptr(col_idx), _ptr(w), _ptr(ws), int(ws_bytes.value),
-                            _ptr(gc), _ptr(gx), _ptr(status), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
-    _check(rc, "kb_adjoint_lower")
-    if check:
-        torch.cuda.current_stream().synchronize()
-        _raise_on_flags(int(status[0].item()) & 0xFFFFFFFF, allow_flags)
-    return gc, gx
+    a = AdjointBuilder(elem, conn.shape[0], coords.shape[0], device=conn.device)
+    a.run(conn, coords, coef, row_ptr, col_idx, w)
+    if not check:
+        return a.grad_coef, a.grad_coords
+    return a.result(check=True, allow_flags=allow_flags)
 
 
 class _LowerK(torch.autograd.Function):
@@ -526,7 +551,8 @@ def default_candidates(elem: int, prec="fp32fb64"):
 
 
 __all__ = ["Builder", "BatchBuilder", "Batch", "LowerCSR", "KBuildError", "Tuning", "build_lower_csr",
-           "build_lower_csr_batched", "assemble_lower_csr", "integrate_lower", "adjoint_lower", "lower_csr_values",
+           "build_lower_csr_batched", "assemble_lower_csr", "integrate_lower", "adjoint_lower", "AdjointBuilder",
+           "lower_csr_values",
            "pack_batch", "plan", "plan_batched",
            "autotune", "default_candidates", "status_string", "version", "value_dtype", "STAGE_NAMES", "KB_N_STAGES",
            "KB_HEX8", "KB_TET4", "KB_FP64", "KB_FP32", "KB_FP32_FB64", "KB_OP_STIFFNESS", "KB_OP_MASS"]

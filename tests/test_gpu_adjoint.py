@@ -70,6 +70,32 @@ def test_adjoint_bitwise_deterministic():
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
+def test_reusable_adjoint_context():
+    """AdjointBuilder: the same buffers over several calls, with different weights and a
+    stale status from a flagged call in between, give the one-shot results bit for bit."""
+    m = MESHES["hex_perm"]
+    conn, coords, coef = to_dev(m)
+    r = kb.build_lower_csr(conn, coords, coef, m.elem, prec="fp64")
+    rp, col = r.row_ptr.clone(), r.col_idx.clone()
+    a = kb.AdjointBuilder(m.elem, m.n_elem, m.n_node, device=conn.device)
+    ws0 = a.ws.data_ptr()
+    for seed in (1, 2):
+        w = torch.from_numpy(np.random.default_rng(seed).standard_normal(r.nnz)).to(conn.device)
+        a.run(conn, coords, coef, rp, col, w)
+        gc, gx = (t.clone() for t in a.result())
+        ref = kb.adjoint_lower(conn, coords, coef, m.elem, rp, col, w)
+        assert torch.equal(gc, ref[0]) and torch.equal(gx, ref[1])
+        if seed == 1:  # a flagged call: its status must not leak into the next one
+            bad = conn.clone()
+            bad[0, 0] = m.n_node
+            a.run(bad, coords, coef, rp, col, w)
+            with pytest.raises(kb.KBuildError):
+                a.result()
+    assert a.ws.data_ptr() == ws0
+    with pytest.raises(ValueError):
+        a.run(conn[:-1], coords, coef[:-1], rp, col, w)
+
+
 def test_autograd_function():
     m = MESHES["hex_perm"]
     conn, coords, coef = to_dev(m)
