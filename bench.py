@@ -119,7 +119,10 @@ def parse():
     ap.add_argument("--prec", default=None, choices=["fp64", "fp32", "fp32fb64"])
     ap.add_argument("--no-fp64", action="store_true", help="skip the all-FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-sample", type=int, default=10_000_000, help="elements in the oracle's timed sample")
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help="elements in the oracle's timed sample (0: as many as make 202.5M lower pairs, i.e. the "
+                         "whole 20.25M-tet workload)")
+    ap.add_argument("--copy-mib", type=int, default=2048, help="size of the device copy timed as a ceiling (0: skip)")
     ap.add_argument("--profile-steps", action="store_true", help="no stage events (for profiler runs)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
@@ -279,7 +282,17 @@ class BatchTotals:
         self.nnz, self.n_fallback = nnz, n_fallback
 
 
+def default_cpu_sample(elem: int) -> int:
+    """Elements of the oracle's timed sample: as many as make 202.5M lower pairs (the whole
+    20.25M-tet workload; 5.6M bricks), about 10-30 s of single-threaded oracle work."""
+    return 202_500_000 // (elem * (elem + 1) // 2)
+
+
 def cpu_baseline(m, sample):
+    """The single-threaded FP64 oracle timed on the first ``sample`` elements, then the
+    all-cores harness (same element routine, parallel loops and sort) on the same
+    sample.  Returns (single-threaded record, all-cores record, oracle CSR of the sample
+    or None when the sample is part of the workload)."""
     import numpy as np
 
     import meshgen
@@ -293,18 +306,78 @@ def cpu_baseline(m, sample):
             done += m[k].n_elem
             k += 1
         dt = time.perf_counter() - t
-        return {"value": done / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
-                "sample": f"the first {k} of {len(m)} meshes ({done:,} elements), each built separately by the "
-                          f"single-threaded FP64 C oracle, {dt:.1f} s"}
+        single = {"value": done / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
+                  "sample": f"the first {k} of {len(m)} meshes ({done:,} elements), each built separately by the "
+                            f"single-threaded FP64 C oracle, {dt:.1f} s"}
+        th = oracle.par_threads()
+        t = time.perf_counter()
+        for x in m[:k]:
+            oracle.par_build_mesh(x)
+        dtp = time.perf_counter() - t
+        par = {"value": done / dtp, "unit": "elements/s", "cores": th, "kind": "oracle, all-cores harness",
+               "sample": f"the same {k} meshes, {dtp:.1f} s"}
+        return single, par, None
     n = min(sample, m.n_elem)
-    sub = meshgen.Mesh(m.elem, np.ascontiguousarray(m.conn[:n]), m.coords, np.ascontiguousarray(m.coef[:n]))
+    whole = n == m.n_elem
+    sub = m if whole else meshgen.Mesh(m.elem, np.ascontiguousarray(m.conn[:n]), m.coords,
+                                       np.ascontiguousarray(m.coef[:n]))
     oracle.lib()
     t = time.perf_counter()
-    oracle.build_mesh(sub)
+    ref = oracle.build_mesh(sub)
     dt = time.perf_counter() - t
-    return {"value": n / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n:,} of the {m.n_elem:,} elements (all {m.n_node:,} nodes), single-threaded FP64 "
-                      f"C oracle, integrate + sort + CSR, {dt:.1f} s"}
+    what = (f"all {n:,} elements" if whole else f"first {n:,} of the {m.n_elem:,} elements (all {m.n_node:,} "
+            f"nodes)")
+    single = {"value": n / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
+              "sample": f"{what}, single-threaded FP64 C oracle, integrate + sort + CSR, {dt:.1f} s"}
+    th = oracle.par_threads()
+    t = time.perf_counter()
+    oracle.par_build_mesh(sub)
+    dtp = time.perf_counter() - t
+    par = {"value": n / dtp, "unit": "elements/s", "cores": th, "kind": "oracle, all-cores harness",
+           "sample": f"{what}, the oracle's element routine on {th} OpenMP threads with a parallel merge sort "
+                     f"(oracle/timing_par.c), {dtp:.1f} s"}
+    return single, par, (ref if whole else None)
+
+
+def scaled_errors(results: dict, ref) -> dict:
+    """Diagonal-scaled error max |dK_ij| / sqrt(K_ii K_jj) of each benched run against the
+    oracle's matrix; the pattern must match exactly (else the error is reported as inf)."""
+    import numpy as np
+
+    orp, ocol, oval, _ = ref
+    n = len(orp) - 1
+    last = orp[1:] - 1
+    diag = np.where(orp[1:] > orp[:-1], oval[np.maximum(last, 0)], 0.0)
+    rows = np.repeat(np.arange(n), np.diff(orp))
+    scale = np.sqrt(np.abs(diag[rows] * diag[ocol]))
+    scale = np.where(scale > 0, scale, 1.0)
+    out = {}
+    for prec, (rp, col, val) in results.items():
+        if not (np.array_equal(rp, orp) and np.array_equal(col, ocol)):
+            out[prec] = float("inf")
+            continue
+        out[prec] = float(np.max(np.abs(val.astype(np.float64) - oval) / scale)) if len(oval) else 0.0
+    return out
+
+
+def copy_ceiling(torch, mib: int) -> dict:
+    """Rate of a plain device-to-device copy (read + write bytes per second), the
+    practical ceiling of a streaming kernel on this device."""
+    src = torch.ones(mib << 20, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 5
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"bytes": 2 * (mib << 20), "ms": ms, "GBps": 2 * (mib << 20) / (ms * 1e-3) / 1e9}
 
 
 class MeshTotals:
@@ -357,6 +430,10 @@ def main():
     nnz = res.nnz
     print(f"[bench] {prec}: {ms:.3f} ms/step, nnz {nnz}, fallback elements {res.n_fallback}", file=sys.stderr,
           flush=True)
+    host = {}  # the benched runs' CSR on the host, for the error against the oracle
+    if isinstance(res, kb.LowerCSR):
+        host[prec] = (res.row_ptr.cpu().numpy(), res.col_idx.cpu().numpy(), res.vals.cpu().numpy())
+    del res
     value = m.n_elem / (ms * 1e-3)
     ab = algorithmic_bytes(m.elem, m.n_elem, m.n_node, nnz, prec)
     out = {
@@ -390,12 +467,26 @@ def main():
                            # memory system is, wasted bytes (partly used lines) included
                            "traffic_frac": (traffic / (stages[dom] * 1e-3) / 1e9 / HBM_PEAK_GBS) if traffic else None}
         out["stages_ms"] = stages
+        # every stage's algorithmic bytes over its time, against the HBM peak
+        out["stage_hbm_frac"] = {k: ab[k] / (stages[k] * 1e-3) / (HBM_PEAK_GBS * 1e9)
+                                 for k in ("count", "integrate", "histogram", "partition", "reduce", "compress")
+                                 if stages.get(k, 0) > 0}
+    if args.copy_mib:
+        cc = copy_ceiling(torch, args.copy_mib)
+        out["copy_ceiling"] = {"GBps": cc["GBps"], "bytes": cc["bytes"], "ms": cc["ms"],
+                               "path_frac": ab["path"] / (ms * 1e-3) / (cc["GBps"] * 1e9)}
+        if out.get("roofline"):
+            out["copy_ceiling"]["dominant_kernel_frac"] = out["roofline"]["achieved"] / cc["GBps"]
+        print(f"[bench] device copy {cc['GBps']:.0f} GB/s", file=sys.stderr, flush=True)
     if not args.no_fp64 and prec != "fp64":
         ms64, _, st64, r64 = time_builds(kb, torch, mesh_dev, m, "fp64", max(3, args.steps // 2), 2,
                                          stage_events=False, tuning=kb.Tuning(bucket_bits=args.bucket_bits,
                                                                               sub_bits=args.sub_bits), op=args.op,
                                          groups=groups)
         out["fp64"] = {"ms_per_step": ms64, "value": m.n_elem / (ms64 * 1e-3)}
+        if isinstance(r64, kb.LowerCSR):
+            host["fp64"] = (r64.row_ptr.cpu().numpy(), r64.col_idx.cpu().numpy(), r64.vals.cpu().numpy())
+        del r64
         out["speedup_vs_fp64"] = ms64 / ms
         print(f"[bench] fp64: {ms64:.3f} ms/step", file=sys.stderr, flush=True)
     if args.adjoint and cid != 4:
@@ -403,12 +494,20 @@ def main():
         print(f"[bench] adjoint: {out['adjoint']['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
     if args.dof > 1 and cid != 4:
         out["dof_assembly"] = time_dof(kb, torch, mesh_dev, m, prec, args.dof, args.steps, args.warmup,
-                                       0 if args.no_cpu else max(1, args.cpu_sample // (10 * args.dof * args.dof)))
+                                       0 if args.no_cpu else max(1, 1_000_000 // (args.dof * args.dof)))
         print(f"[bench] dof {args.dof} assembly: {out['dof_assembly']['ms_per_step']:.3f} ms/step", file=sys.stderr,
               flush=True)
     if not args.no_cpu:
-        print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(meshes if cid == 4 else m, args.cpu_sample)
+        sample = args.cpu_sample or default_cpu_sample(m.elem)
+        print(f"[bench] timing the CPU oracle on {min(sample, m.n_elem):,} elements", file=sys.stderr, flush=True)
+        single, par, ref = cpu_baseline(meshes if cid == 4 else m, sample)
+        out["cpu_baseline"] = single
+        out["cpu_baseline_all_cores"] = par
+        if ref is not None and host and args.op == "stiffness":
+            err = scaled_errors(host, ref)
+            out["scaled_error"] = {"vs": "FP64 oracle, every entry", "metric": "max |dK_ij| / sqrt(K_ii K_jj)",
+                                   **err, "tolerance": {k: (1e-12 if k == "fp64" else 5e-6) for k in err}}
+            print(f"[bench] scaled error against the oracle: {err}", file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
 
 

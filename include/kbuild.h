@@ -58,7 +58,7 @@
 extern "C" {
 #endif
 
-#define KB_VERSION 1
+#define KB_VERSION 2
 
 /* element types (value = nodes per element) */
 #define KB_HEX8 8
@@ -273,19 +273,27 @@ int kb_build_lower_csr_batched(const kb_batch* batch, int prec, const kb_tuning*
 /*
  * Adjoint (not part of the paper; derived from Eq. 7-9).  For the loss
  * L = sum over the lower pattern of w_ij K_ij, with w (device double [nnz]) laid out
- * like the values of the lower CSR (row_ptr, col_idx) that kb_build_lower_csr produced
- * for this mesh, writes
+ * like the values of the lower CSR (row_ptr [n_node + 1], col_idx [nnz]) that
+ * kb_build_lower_csr produced for this mesh, writes
  *   grad_coef   device double [n_elem]     dL/dc_e,
  *   grad_coords device double [n_node][3]  dL/dX (x, y, z of each node).
+ * nnz is the number of entries of col_idx and w: no entry outside [0, nnz) is read,
+ * and a row whose pointers fall outside it counts as missing from the pattern.
  * All arithmetic is FP64 whatever precision built K.  Node gradients are summed exactly
  * (fixed-point integers), so the output is bitwise deterministic; exact while no node
  * belongs to more than 65,536 elements.  A node pair of an element that is missing
  * from the pattern sets KB_F_INDEX (its weight is taken as 0); elements with index
- * errors contribute nothing.  Workspace from kb_plan_adjoint (host only).
+ * errors contribute nothing.  An element whose Jacobian determinant is not > 0 at some
+ * integration point sets KB_F_INVERTED; one whose gradients are not finite (degenerate
+ * geometry, non-finite coordinates or coefficient) sets KB_F_NONFINITE, and its
+ * non-finite node contributions are left out of the sums.  Workspace from
+ * kb_plan_adjoint (host only).  Errors: KB_EINVAL (bad argument, nnz < 0), KB_ERANGE
+ * (nnz beyond int32 indexing).
  */
 int kb_plan_adjoint(const kb_mesh* mesh, size_t* ws_bytes);
-int kb_adjoint_lower(const kb_mesh* mesh, const int32_t* row_ptr, const int32_t* col_idx, const double* w, void* ws,
-                     size_t ws_bytes, double* grad_coef, double* grad_coords, uint32_t* status_dev, void* stream);
+int kb_adjoint_lower(const kb_mesh* mesh, const int32_t* row_ptr, const int32_t* col_idx, const double* w,
+                     int64_t nnz, void* ws, size_t ws_bytes, double* grad_coef, double* grad_coords,
+                     uint32_t* status_dev, void* stream);
 
 /* Static text for a return code (negative) or a single status flag bit (positive). */
 const char* kb_status_string(int code);

@@ -154,6 +154,48 @@ def build_mesh(mesh):
     return build_lower_csr(mesh.elem, mesh.conn, mesh.coords, mesh.coef)
 
 
+_par = None
+
+
+def par_build_mesh(mesh, threads: int = 0):
+    """The oracle's construction on ``threads`` host threads (0: all), for timing: the
+    same element routine, parallel loops and sort (``timing_par.c``).  Returns
+    (row_ptr, col_idx, vals, flags); values agree with build_mesh to rounding."""
+    global _par
+    if _par is None:
+        if not os.path.exists(_build.PAR_LIB):
+            _build.build()
+        L = ctypes.CDLL(_build.PAR_LIB)
+        i64, i32, p = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p
+        L.orc_par_build_lower_csr.argtypes = [i32, i64, i64, p, p, p, p, p, p, i64, p, i32]
+        L.orc_par_build_lower_csr.restype = i64
+        L.orc_par_max_threads.argtypes = []
+        L.orc_par_max_threads.restype = i32
+        _par = L
+    conn = _c(mesh.conn, np.int32)
+    coords = _c(mesh.coords, np.float64)
+    coef = _c(mesh.coef, np.float64)
+    nn = coords.shape[0]
+    cap = conn.shape[0] * mesh.elem * (mesh.elem + 1) // 2
+    row_ptr = np.zeros(nn + 1, np.int32)
+    col = np.zeros(max(cap, 1), np.int32)
+    val = np.zeros(max(cap, 1))
+    flags = np.zeros(1, np.uint32)
+    nnz = _par.orc_par_build_lower_csr(mesh.elem, conn.shape[0], nn, _p(conn), _p(coords), _p(coef), _p(row_ptr),
+                                       _p(col), _p(val), cap, _p(flags), int(threads))
+    if nnz < 0:
+        raise ValueError("bad arguments")
+    return row_ptr, col[:nnz], val[:nnz], int(flags[0])
+
+
+def par_threads() -> int:
+    """Threads the all-cores harness uses by default (OpenMP's count on this host)."""
+    if _par is None:
+        par_build_mesh(type("M", (), dict(elem=4, conn=np.zeros((0, 4), np.int32), coords=np.zeros((0, 3)),
+                                          coef=np.zeros(0)))())
+    return int(_par.orc_par_max_threads())
+
+
 def adjoint_lower(mesh, row_ptr, col_idx, w):
     """(dL/dc [n_elem], dL/dX [n_node, 3]) of L = sum W_ij K_ij over the lower pattern
     (row_ptr, col_idx) of the mesh's K, W aligned with that pattern.  FP64."""

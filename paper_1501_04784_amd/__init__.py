@@ -342,11 +342,17 @@ class AdjointBuilder:
         _validate_mesh(conn, coords, coef, self.elem)
         if conn.shape[0] != self.n_elem or coords.shape[0] != self.n_node:
             raise ValueError("mesh shape differs from the one this context was made for")
-        if w.dtype != torch.float64 or w.numel() != col_idx.numel() or not w.is_contiguous():
-            raise ValueError("w must be a contiguous float64 tensor with one weight per pattern entry")
+        for name, t in (("row_ptr", row_ptr), ("col_idx", col_idx)):
+            if t.dtype != torch.int32 or t.dim() != 1 or not t.is_contiguous() or t.device != conn.device:
+                raise ValueError(f"{name} must be a contiguous int32 vector on the mesh's device")
+        if row_ptr.numel() != self.n_node + 1:
+            raise ValueError(f"row_ptr must have n_node + 1 = {self.n_node + 1} entries")
+        if (w.dtype != torch.float64 or w.dim() != 1 or w.numel() != col_idx.numel() or not w.is_contiguous()
+                or w.device != conn.device):
+            raise ValueError("w must be a contiguous float64 device vector with one weight per pattern entry")
         m = _mesh(self.elem, self.n_elem, self.n_node, conn, coords, coef)
-        rc = _lib.lib().kb_adjoint_lower(ctypes.byref(m), _ptr(row_ptr), _ptr(col_idx), _ptr(w), _ptr(self.ws),
-                                         self.ws_bytes, _ptr(self.grad_coef), _ptr(self.grad_coords),
+        rc = _lib.lib().kb_adjoint_lower(ctypes.byref(m), _ptr(row_ptr), _ptr(col_idx), _ptr(w), int(col_idx.numel()),
+                                         _ptr(self.ws), self.ws_bytes, _ptr(self.grad_coef), _ptr(self.grad_coords),
                                          _ptr(self.status), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
         _check(rc, "kb_adjoint_lower")
 

@@ -95,7 +95,7 @@ def lib():
         L.kb_build_lower_csr_batched.restype = i32
         L.kb_plan_adjoint.argtypes = [PM, ctypes.POINTER(sz)]
         L.kb_plan_adjoint.restype = i32
-        L.kb_adjoint_lower.argtypes = [PM, p, p, p, p, sz, p, p, p, p]
+        L.kb_adjoint_lower.argtypes = [PM, p, p, p, i64, p, sz, p, p, p, p]
         L.kb_adjoint_lower.restype = i32
         L.kb_status_string.argtypes = [i32]
         L.kb_status_string.restype = ctypes.c_char_p

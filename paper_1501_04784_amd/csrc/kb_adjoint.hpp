@@ -26,10 +26,14 @@
 
 namespace kb {
 
-// position of (row, col) in a lower CSR with ascending columns, or -1
+// position of (row, col) in a lower CSR with ascending columns, or -1.  The search is
+// confined to [0, nnz), the length of col_idx: a row range outside it (a row pointer
+// that does not belong to this col_idx) also gives -1.
 __device__ __forceinline__ int64_t csr_position(const int32_t* __restrict__ row_ptr,
-                                                const int32_t* __restrict__ col_idx, int32_t row, int32_t col) {
+                                                const int32_t* __restrict__ col_idx, int64_t nnz, int32_t row,
+                                                int32_t col) {
   int64_t lo = row_ptr[row], hi = (int64_t)row_ptr[row + 1] - 1;
+  if (lo < 0 || hi >= nnz || lo > hi + 1) return -1;
   while (lo <= hi) {
     const int64_t mid = (lo + hi) >> 1;
     const int32_t c = col_idx[mid];
@@ -84,7 +88,7 @@ __global__ __launch_bounds__(128) void k_adjoint_elems(const int32_t* __restrict
                                                        const double* __restrict__ coords,
                                                        const double* __restrict__ coef, int64_t n_elem,
                                                        int64_t n_node, const int32_t* __restrict__ row_ptr,
-                                                       const int32_t* __restrict__ col_idx,
+                                                       const int32_t* __restrict__ col_idx, int64_t nnz,
                                                        const double* __restrict__ w,
                                                        double* __restrict__ grad_coef, double* __restrict__ gel,
                                                        uint32_t* __restrict__ emax, uint32_t* __restrict__ status) {
@@ -110,7 +114,7 @@ __global__ __launch_bounds__(128) void k_adjoint_elems(const int32_t* __restrict
 #pragma unroll
         for (int b = 0; b <= a; ++b) {
           const int32_t row = E[a] > E[b] ? E[a] : E[b], col = E[a] > E[b] ? E[b] : E[a];
-          const int64_t k = csr_position(row_ptr, col_idx, row, col);
+          const int64_t k = csr_position(row_ptr, col_idx, nnz, row, col);
           if (k < 0) f |= KB_F_INDEX;
           const double v = k < 0 ? 0.0 : w[k];
           S[lidx(a, b)] = a == b ? v : 0.5 * v;
@@ -137,6 +141,7 @@ __global__ __launch_bounds__(128) void k_adjoint_elems(const int32_t* __restrict
             }
           double A[3][3];
           const double det = adjugate(J, A);
+          if (!(det > 0.0)) f |= KB_F_INVERTED;
           double G[3][8];
 #pragma unroll
           for (int i = 0; i < 3; ++i)
@@ -154,6 +159,7 @@ __global__ __launch_bounds__(128) void k_adjoint_elems(const int32_t* __restrict
           for (int j = 0; j < 3; ++j) J[i][j] = X[i + 1][j];
         double A[3][3];
         const double det = adjugate(J, A);
+        if (!(det > 0.0)) f |= KB_F_INVERTED;
         double G[3][4];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
@@ -165,6 +171,14 @@ __global__ __launch_bounds__(128) void k_adjoint_elems(const int32_t* __restrict
         adjoint_point<4>(G, S, det, 1.0 / 6.0, c, &gc, D);
       }
     }
+    // a degenerate or inverted element, or non-finite input, gives non-finite gradients:
+    // flagged, and their node contributions are dropped (the exact sums take 0 for them)
+    bool finite = isfinite(gc);
+#pragma unroll
+    for (int a = 0; a < NEN; ++a)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) finite = finite && isfinite(D[a][j]);
+    if (!finite) f |= KB_F_NONFINITE;
     if (f) raise_flag(status, f);
     grad_coef[e] = gc;
 #pragma unroll

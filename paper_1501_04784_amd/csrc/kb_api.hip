@@ -904,9 +904,9 @@ int kb_build_lower_csr_batched(const kb_batch* batch, int prec, const kb_tuning*
   if (p.nel > 0 && nm > 0) {
     const unsigned g = (unsigned)std::min<int64_t>(div_up(p.nel, 256), 65536);
     if (p.nen == 8)
-      k_batch_conn<8><<<g, 256, 0, s>>>(batch->conn, batch->elem_off, batch->node_off, nm, p.nel, gconn);
+      k_batch_conn<8><<<g, 256, 0, s>>>(batch->conn, batch->elem_off, batch->node_off, nm, p.nel, flags, gconn);
     else
-      k_batch_conn<4><<<g, 256, 0, s>>>(batch->conn, batch->elem_off, batch->node_off, nm, p.nel, gconn);
+      k_batch_conn<4><<<g, 256, 0, s>>>(batch->conn, batch->elem_off, batch->node_off, nm, p.nel, flags, gconn);
     KB_LAUNCH_CHECK();
     m.conn = gconn;
   }
@@ -918,11 +918,10 @@ int kb_build_lower_csr_batched(const kb_batch* batch, int prec, const kb_tuning*
   else
     KB_TRY(dispatch_build<4>(p, &m, nullptr, w, uptr, col_idx, vals, cap, nnz_off + nm, status_dev, ev, s));
   if (nm > 0) {
-    if (p.nn > 0) {
-      k_batch_rows<<<(unsigned)std::min<int64_t>(div_up(p.nn, 256), 65536), 256, 0, s>>>(uptr, batch->node_off, nm,
-                                                                                          p.nn, cap, col_idx, row_ptr);
-      KB_LAUNCH_CHECK();
-    }
+    // (also with no nodes: failed offsets zero all n_node + n_mesh row pointers)
+    k_batch_rows<<<(unsigned)std::min<int64_t>(div_up(p.nn + nm, 256), 65536), 256, 0, s>>>(
+        uptr, batch->node_off, nm, p.nn, cap, flags, col_idx, row_ptr);
+    KB_LAUNCH_CHECK();
     k_batch_meshes<<<grid_for(nm, 256), 256, 0, s>>>(uptr, batch->node_off, nm, flags, row_ptr, nnz_off, status_dev);
     KB_LAUNCH_CHECK();
   } else {
@@ -958,14 +957,16 @@ int kb_plan_adjoint(const kb_mesh* mesh, size_t* ws_bytes) {
   return KB_OK;
 }
 
-int kb_adjoint_lower(const kb_mesh* mesh, const int32_t* row_ptr, const int32_t* col_idx, const double* w, void* ws,
-                     size_t ws_bytes, double* grad_coef, double* grad_coords, uint32_t* status_dev, void* stream) {
+int kb_adjoint_lower(const kb_mesh* mesh, const int32_t* row_ptr, const int32_t* col_idx, const double* w,
+                     int64_t nnz, void* ws, size_t ws_bytes, double* grad_coef, double* grad_coords,
+                     uint32_t* status_dev, void* stream) {
   size_t o_gel, o_acc, o_emax, total;
   KB_TRY(adjoint_layout(mesh, &o_gel, &o_acc, &o_emax, &total));
   KB_TRY(check_mesh_ptrs(mesh, true));
   if (!status_dev || !ws) return KB_EINVAL;
   if (ws_bytes < total) return KB_ENOSPC;
-  if (mesh->n_elem > 0 && (!row_ptr || !col_idx || !w || !grad_coef)) return KB_EINVAL;
+  if (nnz < 0 || nnz >= (int64_t)INT32_MAX) return nnz < 0 ? KB_EINVAL : KB_ERANGE;
+  if (mesh->n_elem > 0 && (!row_ptr || !grad_coef || (nnz > 0 && (!col_idx || !w)))) return KB_EINVAL;
   if (mesh->n_node > 0 && !grad_coords) return KB_EINVAL;
   auto s = (hipStream_t)stream;
   auto* wsb = (unsigned char*)ws;
@@ -984,11 +985,11 @@ int kb_adjoint_lower(const kb_mesh* mesh, const int32_t* row_ptr, const int32_t*
   if (nel > 0) {
     const unsigned ge = grid_for(nel, 128);
     if (nen == 8)
-      k_adjoint_elems<8><<<ge, 128, 0, s>>>(mesh->conn, mesh->coords, mesh->coef, nel, nn, row_ptr, col_idx, w,
-                                            grad_coef, gel, emax, status_dev);
+      k_adjoint_elems<8><<<ge, 128, 0, s>>>(mesh->conn, mesh->coords, mesh->coef, nel, nn, row_ptr, col_idx, nnz,
+                                            w, grad_coef, gel, emax, status_dev);
     else
-      k_adjoint_elems<4><<<ge, 128, 0, s>>>(mesh->conn, mesh->coords, mesh->coef, nel, nn, row_ptr, col_idx, w,
-                                            grad_coef, gel, emax, status_dev);
+      k_adjoint_elems<4><<<ge, 128, 0, s>>>(mesh->conn, mesh->coords, mesh->coef, nel, nn, row_ptr, col_idx, nnz,
+                                            w, grad_coef, gel, emax, status_dev);
     KB_LAUNCH_CHECK();
     const unsigned gs = (unsigned)div_up(nel * nen, kScatEntries);
     if (nen == 8)

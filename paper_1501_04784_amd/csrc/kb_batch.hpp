@@ -44,13 +44,21 @@ __global__ void k_batch_check(const int64_t* __restrict__ elem_off, const int64_
 
 // Global connectivity: each element's local ids shifted by its mesh's first node.  A
 // local id outside [0, nodes of the mesh) becomes -1, which the pipeline flags as an
-// index error and leaves out.
+// index error and leaves out.  When the offsets failed their check (*flags set) no
+// element can be placed in a mesh: every id becomes -1.
 template <int NEN>
 __global__ __launch_bounds__(256) void k_batch_conn(const int32_t* __restrict__ conn, const int64_t* __restrict__ elem_off,
                                                     const int64_t* __restrict__ node_off, int64_t n_mesh,
-                                                    int64_t n_elem, int32_t* __restrict__ gconn) {
+                                                    int64_t n_elem, const uint32_t* __restrict__ flags,
+                                                    int32_t* __restrict__ gconn) {
+  const bool bad = *flags != 0;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n_elem;
        e += (int64_t)gridDim.x * blockDim.x) {
+    if (bad) {
+#pragma unroll
+      for (int a = 0; a < NEN; ++a) gconn[e * NEN + a] = -1;
+      continue;
+    }
     const int64_t m = owner_of(elem_off, n_mesh, e);
     const int64_t base = node_off[m], nm = node_off[m + 1] - base;
 #pragma unroll
@@ -63,10 +71,20 @@ __global__ __launch_bounds__(256) void k_batch_conn(const int32_t* __restrict__ 
 
 // One thread per node i of the batch (mesh m): its row in mesh m's own CSR.  row_ptr of
 // mesh m occupies out_ptr[node_off[m] + m .. node_off[m+1] + m]; columns become local.
-// Columns are rewritten only when the union CSR was written (nnz <= cap).
+// Columns are rewritten only when the union CSR was written (nnz <= cap).  Offsets that
+// failed their check (*flags set) say nothing trustworthy about where a mesh's rows
+// go: then every one of the n_node + n_mesh row pointers is written as 0 instead (no
+// element was kept, so the union CSR is empty) and node_off is not read.
 __global__ __launch_bounds__(256) void k_batch_rows(const int32_t* __restrict__ uptr, const int64_t* __restrict__ node_off,
                                                     int64_t n_mesh, int64_t n_node, int64_t cap,
+                                                    const uint32_t* __restrict__ flags,
                                                     int32_t* __restrict__ col_idx, int32_t* __restrict__ out_ptr) {
+  if (*flags) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_node + n_mesh;
+         i += (int64_t)gridDim.x * blockDim.x)
+      out_ptr[i] = 0;
+    return;
+  }
   const int64_t nnz = uptr[n_node];
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_node;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -80,13 +98,19 @@ __global__ __launch_bounds__(256) void k_batch_rows(const int32_t* __restrict__ 
 
 // One thread per mesh: its closing row pointer and its first entry in col_idx / vals;
 // nnz_off[n_mesh] already holds the batch total.  Folds the offset-check flags into the
-// status word.
+// status word.  With failed offsets (*flags set) node_off is not read: every mesh gets
+// the empty range nnz_off[m] = 0 (k_batch_rows has zeroed the row pointers).
 __global__ void k_batch_meshes(const int32_t* __restrict__ uptr, const int64_t* __restrict__ node_off,
                                int64_t n_mesh, const uint32_t* __restrict__ flags, int32_t* __restrict__ out_ptr,
                                int64_t* __restrict__ nnz_off, uint32_t* __restrict__ status) {
   const int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (m == 0 && *flags) atomicOr(status, *flags);
+  const uint32_t bad = *flags;
+  if (m == 0 && bad) atomicOr(status, bad);
   if (m >= n_mesh) return;
+  if (bad) {
+    nnz_off[m] = 0;
+    return;
+  }
   const int64_t b = node_off[m], e = node_off[m + 1];
   out_ptr[e + m] = uptr[e] - uptr[b];
   nnz_off[m] = uptr[b];

@@ -16,10 +16,11 @@ def csr_diag(row_ptr, col, val, n):
     """Diagonal of a lower CSR whose rows end with the diagonal entry (0 if absent)."""
     d = np.zeros(n)
     rp = np.asarray(row_ptr, np.int64)
-    for i in range(n):
-        s, e = rp[i], rp[i + 1]
-        if e > s and col[e - 1] == i:
-            d[i] = val[e - 1]
+    last = rp[1:n + 1] - 1
+    has = (rp[1:n + 1] > rp[:n])
+    idx = np.nonzero(has)[0]
+    ok = idx[np.asarray(col)[last[idx]] == idx]
+    d[ok] = np.asarray(val, np.float64)[last[ok]]
     return d
 
 

@@ -54,7 +54,7 @@ def _plan(elem, nel, nn, prec=0, tuning=None):
 
 def test_version_and_strings():
     L = _lib.lib()
-    assert L.kb_version() == 1
+    assert L.kb_version() == 2
     assert L.kb_status_string(0) == b"ok"
     assert L.kb_status_string(-3) == b"workspace too small"
     assert L.kb_status_string(16) == b"nnz exceeds capacity"
@@ -194,14 +194,16 @@ def test_plan_adjoint_and_argument_errors():
     f = ctypes.c_void_p(0x1000)
 
     def call(**kw):
-        a = dict(rp=f, col=f, w=f, ws=f, wsb=ws.value, gc=f, gx=f, st=f)
+        a = dict(rp=f, col=f, w=f, nnz=10, ws=f, wsb=ws.value, gc=f, gx=f, st=f)
         a.update(kw)
-        return L.kb_adjoint_lower(ctypes.byref(m), a["rp"], a["col"], a["w"], a["ws"], a["wsb"], a["gc"], a["gx"],
-                                  a["st"], None)
+        return L.kb_adjoint_lower(ctypes.byref(m), a["rp"], a["col"], a["w"], a["nnz"], a["ws"], a["wsb"], a["gc"],
+                                  a["gx"], a["st"], None)
 
     assert call(wsb=ws.value - 1) == _lib.KB_ENOSPC
     for k in ("rp", "col", "w", "ws", "gc", "gx", "st"):
         assert call(**{k: None}) == _lib.KB_EINVAL, k
+    assert call(nnz=-1) == _lib.KB_EINVAL
+    assert call(nnz=1 << 31) == _lib.KB_ERANGE
     bad = KbMesh(5, 0, 100, 200, 0x1000, 0x1000, 0x1000)
     assert L.kb_plan_adjoint(ctypes.byref(bad), ctypes.byref(ws)) == _lib.KB_EINVAL
 

@@ -136,3 +136,45 @@ def test_adjoint_c5_full():
     ec, ex = rel_err(gc.cpu().numpy(), ogc), rel_err(gx.cpu().numpy(), ogx)
     say(f"[adjoint-c5] dL/dc {ec:.2e}  dL/dX {ex:.2e}")
     assert ec <= TOL and ex <= TOL
+
+
+def test_degenerate_element_is_flagged():
+    """Two tets sharing a face, the second flat (its fourth node in the shared face):
+    det = 0 there.  The adjoint flags it (inverted, non-finite) and leaves its node
+    contributions out; the first element's own gradients still match the oracle."""
+    X = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1], [1 / 3, 1 / 3, 1 / 3]], float)
+    m = meshgen.Mesh(4, np.array([[0, 1, 2, 3], [1, 2, 3, 4]], np.int32), X, np.array([1.5, 0.5]))
+    conn, coords, coef = to_dev(m)
+    allow = kb._lib.KB_F_INVERTED | kb._lib.KB_F_NONFINITE
+    r = kb.build_lower_csr(conn, coords, coef, 4, prec="fp64", check=False)
+    w = torch.from_numpy(np.random.default_rng(3).standard_normal(r.nnz)).to(conn.device)
+    a = kb.AdjointBuilder(4, 2, 5, device=conn.device)
+    a.run(conn, coords, coef, r.row_ptr, r.col_idx, w)
+    gc, gx = a.result(check=False)
+    flags = int(a.status[0].item()) & 0xFFFFFFFF
+    assert flags & kb._lib.KB_F_INVERTED and flags & kb._lib.KB_F_NONFINITE
+    assert flags & ~allow == 0
+    assert bool(torch.isfinite(gx).all())  # the flat element's contributions are dropped
+    ogc, ogx, _ = oracle.adjoint_lower(m, r.row_ptr.cpu().numpy(), r.col_idx.cpu().numpy(), w.cpu().numpy())
+    assert abs(float(gc[0]) - ogc[0]) <= TOL * abs(ogc[0])
+    # node 0 touches only the first element
+    assert float((gx[0].cpu() - torch.from_numpy(ogx[0])).abs().max()) <= TOL * float(np.abs(ogx[0]).max())
+    with pytest.raises(kb.KBuildError):
+        a.result(check=True)
+
+
+def test_row_pointers_outside_the_pattern_are_flagged():
+    """A row pointer beyond the pattern's length is confined by nnz: index flag, no read
+    outside col_idx / w.  Wrongly typed or sized row pointers are refused on the host."""
+    m = MESHES["tet_perm"]
+    conn, coords, coef = to_dev(m)
+    r = kb.build_lower_csr(conn, coords, coef, m.elem, prec="fp64")
+    rp = r.row_ptr.clone()
+    rp[-1] = r.nnz + 1000  # the last row now reaches past col_idx
+    w = torch.ones(r.nnz, dtype=torch.float64, device=conn.device)
+    with pytest.raises(kb.KBuildError):
+        kb.adjoint_lower(conn, coords, coef, m.elem, rp, r.col_idx, w)
+    with pytest.raises(ValueError):
+        kb.adjoint_lower(conn, coords, coef, m.elem, r.row_ptr.long(), r.col_idx, w)
+    with pytest.raises(ValueError):
+        kb.adjoint_lower(conn, coords, coef, m.elem, r.row_ptr[:-1], r.col_idx, w)

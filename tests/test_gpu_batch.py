@@ -165,3 +165,28 @@ def test_batch_256_bricks_sampled():
     err = check_against_oracle([meshes[i] for i in pick], [res[i] for i in pick], "fp32fb64")
     say(f"  sampled worst scaled error {err:.3e}")
     assert err <= TOL["fp32fb64"]
+
+
+@pytest.mark.parametrize("case", ["overshoot", "decreasing"])
+def test_batch_bad_node_offsets_stay_in_bounds(case):
+    """Node offsets that overshoot the node count or decrease: flagged (KB_F_INDEX), and
+    every output is written inside its buffer (row pointers and entry offsets zeroed)."""
+    meshes = small_batch(8, 4, seed=9)
+    batch = kb.pack_batch(as_tuples(meshes), 8)
+    no = batch.node_off.clone()
+    n_node = int(batch.coords.shape[0])
+    if case == "overshoot":
+        no[1] = n_node + 10  # then decreasing back to the total
+    else:
+        no[2] = max(int(no[1]) - 3, 0)
+    batch = kb.Batch(batch.elem, batch.conn, batch.coords, batch.coef, batch.elem_off, no)
+    b = kb.BatchBuilder(batch, prec="fp64")
+    b.row_ptr.fill_(-7)
+    b.nnz_off.fill_(-7)
+    b.run()
+    torch.cuda.synchronize()
+    assert (int(b.status[0].item()) & kb._lib.KB_F_INDEX) != 0
+    assert int(b.row_ptr.abs().sum().item()) == 0
+    assert int(b.nnz_off.abs().sum().item()) == 0
+    with pytest.raises(kb.KBuildError):
+        b.results(check=True)
