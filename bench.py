@@ -132,11 +132,19 @@ def parse():
                     help="also time the adjoint (dL/dc, dL/dX of L = sum W K, seeded N(0,1) weights), FP64")
     ap.add_argument("--groups", type=int, default=0,
                     help="build in this many element groups (Eq. 10; workload c6 needs at least 2, default 2)")
+    ap.add_argument("--host-stream", action="store_true",
+                    help="grouped builds: also time the groups streamed from pinned host memory (upload of group "
+                         "g+1 overlapping the pass of group g; PCIe-inclusive, reported beside the value)")
     ap.add_argument("--dof", type=int, default=1, choices=[1, 2, 3],
                     help="also time the assembly of k ⊗ I_dof element matrices (several DOFs per node)")
     ap.add_argument("--block", type=int, default=0, help="tuning: element tile / block size")
     ap.add_argument("--bucket-bits", type=int, default=0, help="tuning: log2 rows per first-level bucket")
     ap.add_argument("--sub-bits", type=int, default=0, help="tuning: log2 rows per sub-bucket")
+    ap.add_argument("--seg-pairs", type=int, default=0, help="tuning: pairs per sub-bucket partition segment")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="batch workload: time only the built-in tuning (no tuning search / cache lookup)")
+    ap.add_argument("--tune-cache", default=None, help="JSON cache of tuning choices (default: KBUILD_TUNE_CACHE "
+                                                       "or ~/.cache/kbuild/tuning.json)")
     return ap.parse_args()
 
 
@@ -212,6 +220,53 @@ def time_adjoint(kb, torch, mesh_dev, m, steps, warmup):
     ms = t0.elapsed_time(t1) / steps
     return {"ms_per_step": ms, "value": m.n_elem / (ms * 1e-3), "unit": "elements/s",
             "note": "reusable context: workspace and gradients allocated once, before the timed calls"}
+
+
+def time_host_stream(kb, torch, mesh_dev, m, prec, groups, steps, warmup, device_ms):
+    """Grouped build with connectivity and coefficients streamed from pinned host memory:
+    its time, the time of the uploads alone and how much of the shorter of the two
+    (uploads, device-resident build) the streaming hides."""
+    import meshgen
+
+    conn_h = torch.from_numpy(m.conn).pin_memory()
+    coef_h = torch.from_numpy(m.coef).pin_memory()
+    cap = meshgen.box_nnz(m.elem, m.meta["nx"], m.meta["ny"], m.meta["nz"])
+    sb = kb.StreamedGroupedBuilder(m.elem, m.n_elem, m.n_node, -(-m.n_elem // groups), cap, prec=prec)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        sb.run(conn_h, mesh_dev[1], coef_h)
+    sb.result(check=True)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    for _ in range(steps):
+        sb.run(conn_h, mesh_dev[1], coef_h)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    # the uploads alone (same copies, same staging buffers, one stream)
+    b = sb.base
+    t0.record(stream)
+    for g in range(sb.n_groups):
+        e0, e1 = g * b.group, min(b.n_elem, (g + 1) * b.group)
+        sb.stage_conn[g % 2][: e1 - e0].copy_(conn_h[e0:e1], non_blocking=True)
+        sb.stage_coef[g % 2][: e1 - e0].copy_(coef_h[e0:e1], non_blocking=True)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    up_ms = t0.elapsed_time(t1)
+    host_bytes = m.conn.nbytes + m.coef.nbytes
+    hidden = (up_ms + device_ms - ms) / min(up_ms, device_ms)
+    del sb, conn_h, coef_h
+    torch.cuda.empty_cache()
+    return {"ms_per_step": ms, "elements_per_s_pcie_inclusive": m.n_elem / (ms * 1e-3), "upload_ms": up_ms,
+            "upload_GBps": host_bytes / (up_ms * 1e-3) / 1e9, "device_resident_ms": device_ms,
+            "overlap_hidden_frac": hidden, "groups": sb_groups(m.n_elem, groups),
+            "note": "connectivity and coefficients in pinned host memory, two device staging buffers, uploads on a "
+                    "second stream; coordinates device-resident"}
+
+
+def sb_groups(n_elem, groups):
+    return -(-n_elem // -(-n_elem // groups))
 
 
 def kron_values(torch, k1, elem, dof):
@@ -423,7 +478,17 @@ def main():
     torch.cuda.synchronize()
     print(f"[bench] {m.n_elem} elements, {m.n_node} nodes on device; timing {prec}", file=sys.stderr, flush=True)
 
-    tuning = kb.Tuning(block=args.block, bucket_bits=args.bucket_bits, sub_bits=args.sub_bits)
+    tuning = kb.Tuning(block=args.block, bucket_bits=args.bucket_bits, sub_bits=args.sub_bits,
+                       seg_pairs=args.seg_pairs)
+    tune = None
+    if cid == 4 and not args.no_tune and tuning == kb.Tuning():
+        # the batch takes the tuning search's choice (cached per architecture, element,
+        # precision and size class); the built-in choice is timed beside it below
+        t0 = time.perf_counter()
+        tuning, entry = kb.tune_batch(mesh_dev, prec, cache_path=args.tune_cache)
+        tune = {"tuning": entry["tuning"], "source": entry["source"], "key": entry["key"],
+                "search_s": time.perf_counter() - t0, "candidates_timed": entry.get("candidates_timed")}
+        print(f"[bench] tuning ({entry['source']}): {tuning}", file=sys.stderr, flush=True)
     ms, wall_ms, stages, res = time_builds(kb, torch, mesh_dev, m, prec, args.steps, args.warmup,
                                            stage_events=not args.profile_steps, tuning=tuning, op=args.op,
                                            groups=groups)
@@ -433,6 +498,7 @@ def main():
     host = {}  # the benched runs' CSR on the host, for the error against the oracle
     if isinstance(res, kb.LowerCSR):
         host[prec] = (res.row_ptr.cpu().numpy(), res.col_idx.cpu().numpy(), res.vals.cpu().numpy())
+    n_fallback = res.n_fallback
     del res
     value = m.n_elem / (ms * 1e-3)
     ab = algorithmic_bytes(m.elem, m.n_elem, m.n_node, nnz, prec)
@@ -443,8 +509,9 @@ def main():
         "dtype": "f64" if prec == "fp64" else "f32", "data": "synthetic",
         "config": {"workload": desc if args.op == "stiffness" else desc + ", consistent mass matrix",
                    "n_elem": m.n_elem, "n_node": m.n_node, "nnz": nnz, "precision": prec,
-                   "fp64_fallback_elements": res.n_fallback, "parallelism": "single GPU",
-                   "tuning": {"block": args.block, "bucket_bits": args.bucket_bits, "sub_bits": args.sub_bits},
+                   "fp64_fallback_elements": n_fallback, "parallelism": "single GPU",
+                   "tuning": {"block": tuning.block, "bucket_bits": tuning.bucket_bits, "sub_bits": tuning.sub_bits,
+                              "seg_pairs": tuning.seg_pairs},
                    "groups": groups if groups > 1 else 1},
         "path_hbm_frac": ab["path"] / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
     }
@@ -471,6 +538,14 @@ def main():
         out["stage_hbm_frac"] = {k: ab[k] / (stages[k] * 1e-3) / (HBM_PEAK_GBS * 1e9)
                                  for k in ("count", "integrate", "histogram", "partition", "reduce", "compress")
                                  if stages.get(k, 0) > 0}
+    if tune is not None:
+        # the built-in tuning on the same batch, for comparison with the tuned value
+        msd, _, _, _ = time_builds(kb, torch, mesh_dev, m, prec, args.steps, args.warmup, stage_events=False)
+        tune["default_ms_per_step"] = msd
+        tune["default_value"] = m.n_elem / (msd * 1e-3)
+        tune["speedup_vs_default"] = msd / ms
+        out["autotune"] = tune
+        print(f"[bench] built-in tuning: {msd:.3f} ms/step", file=sys.stderr, flush=True)
     if args.copy_mib:
         cc = copy_ceiling(torch, args.copy_mib)
         out["copy_ceiling"] = {"GBps": cc["GBps"], "bytes": cc["bytes"], "ms": cc["ms"],
@@ -489,6 +564,10 @@ def main():
         del r64
         out["speedup_vs_fp64"] = ms64 / ms
         print(f"[bench] fp64: {ms64:.3f} ms/step", file=sys.stderr, flush=True)
+    if args.host_stream and groups > 1:
+        out["host_stream"] = time_host_stream(kb, torch, mesh_dev, m, prec, groups, max(2, args.steps // 4), 1, ms)
+        print(f"[bench] host-streamed groups: {out['host_stream']['ms_per_step']:.3f} ms/step", file=sys.stderr,
+              flush=True)
     if args.adjoint and cid != 4:
         out["adjoint"] = time_adjoint(kb, torch, mesh_dev, m, args.steps, args.warmup)
         print(f"[bench] adjoint: {out['adjoint']['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)

@@ -28,7 +28,10 @@
  *   KB_FP64       all arithmetic in FP64 (double);
  *   KB_FP32       node coordinates are differenced in FP64 against the element's first
  *                 node, the rest of the integration runs in FP32; assembly sums exactly
- *                 and rounds each entry once (float);
+ *                 and rounds each entry once (float).  Outside the FP32 accuracy bound
+ *                 (5e-6 of sqrt(K_ii K_jj) per entry): the FP32 geometry error grows with
+ *                 the Jacobian's condition number (the tests hold it to 2e-5 on
+ *                 jittered meshes); KB_FP32_FB64 is the mode that meets the bound;
  *   KB_FP32_FB64  as KB_FP32, but an element whose Jacobian at some integration point
  *                 has an estimated infinity-norm condition number above tau gets its
  *                 Jacobian, determinant and inverse in FP64 (float).
@@ -58,7 +61,7 @@
 extern "C" {
 #endif
 
-#define KB_VERSION 2
+#define KB_VERSION 3
 
 /* element types (value = nodes per element) */
 #define KB_HEX8 8
@@ -128,6 +131,10 @@ typedef struct {
   int32_t sub_bits;        /* log2 rows per sub-bucket, <= bucket_bits and <= 8 (0 = auto) */
   void** stage_events;     /* NULL, or KB_N_STAGES + 1 hipEvent_t: event i is recorded
                               on the stream before stage i, the last after the final one */
+  int32_t seg_pairs;       /* pairs per segment of the sub-bucket partition: 4096 or 8192
+                              (0 = from the mesh shape: 8192 for tetrahedra whose short
+                              segments would give fewer than 16 pairs per sub-bucket)   */
+  int32_t reserved;        /* must be 0                                                */
 } kb_tuning;
 
 /*
@@ -137,8 +144,12 @@ typedef struct {
  * nnz (so cap = *n_triplets always suffices).  Either output pointer may be NULL.
  * Only elem, op, n_elem and n_node of the mesh are read.  KB_ERANGE when n_node or T
  * exceeds int32 indexing; KB_EINVAL also when the matrix has more rows than the
- * row buckets can hold (each pass-1 workgroup keeps two counters per bucket in LDS:
- * about 8e7 rows, with the default tuning).
+ * row buckets can hold: each pass-1 workgroup keeps two LDS counters per bucket of at
+ * most 2^16 rows beside its staged pairs, and a sub-bucket key packs the row within its
+ * sub-bucket beside a column index in 31 bits.  Without bucket_bits / sub_bits the plan
+ * widens the buckets (and the sub-buckets) and narrows the element tile as the rows
+ * grow: up to about 1.3e8 rows (2^27; about 7e7 for element matrices of more than 8
+ * rows), where the lower pattern of a brick mesh nears the 2^31 entries of int32 indexing.
  */
 int kb_plan(const kb_mesh* mesh, int prec, const kb_tuning* tuning, size_t* ws_bytes, int64_t* n_triplets);
 
@@ -226,6 +237,29 @@ int kb_plan_grouped(const kb_mesh* mesh, int prec, const kb_tuning* tuning, int6
 int kb_build_lower_csr_grouped(const kb_mesh* mesh, int prec, const kb_tuning* tuning, int64_t group_elems, void* ws,
                                size_t ws_bytes, int32_t* row_ptr, int32_t* col_idx, void* vals, int64_t cap,
                                int64_t* nnz_dev, uint32_t* status_dev, void* stream);
+
+/*
+ * One pass of a grouped build, for callers that stream the element groups in (Eq. 10
+ * groups of a mesh whose connectivity and coefficients stay in host memory: the paper
+ * uploads only the data of the group being integrated, Section 3).  Calling it for
+ * group = 0, 1, ..., n_groups - 1 (n_groups = ceil(n_elem / group_elems)), in order on
+ * one stream with one workspace, gives exactly what kb_build_lower_csr_grouped gives.
+ *   mesh         the whole mesh: elem, op, n_elem, n_node and coords (device, all
+ *                nodes) are read; conn and coef are not (may be NULL)
+ *   group_conn   device [G_g][nen]: the connectivity of elements [group * group_elems,
+ *                group * group_elems + G_g), G_g = min(group_elems, n_elem - group *
+ *                group_elems); group_coef device [G_g] their coefficients.  Only read
+ *                by the work this call enqueues: the caller may refill them once the
+ *                stream has passed it (an event recorded after the call).
+ *   other arguments as for kb_build_lower_csr_grouped (the same workspace and outputs
+ *   on every pass; the outputs hold K after the last pass).
+ * Errors as for kb_build_lower_csr_grouped; KB_EINVAL also for a group outside
+ * [0, n_groups) or a null group array for a non-empty group.
+ */
+int kb_build_lower_csr_group_pass(const kb_mesh* mesh, int prec, const kb_tuning* tuning, int64_t group_elems,
+                                  int64_t group, const int32_t* group_conn, const double* group_coef, void* ws,
+                                  size_t ws_bytes, int32_t* row_ptr, int32_t* col_idx, void* vals, int64_t cap,
+                                  int64_t* nnz_dev, uint32_t* status_dev, void* stream);
 
 /*
  * Batches.  Many independent meshes of one element type, built by one enqueued sequence

@@ -79,9 +79,11 @@ class Tuning:
     bucket_bits: int = 0
     fb_tau: float = 0.0
     sub_bits: int = 0
+    seg_pairs: int = 0
 
     def to_c(self, events=None) -> KbTuning:
-        return KbTuning(int(self.block), int(self.bucket_bits), float(self.fb_tau), int(self.sub_bits), events)
+        return KbTuning(int(self.block), int(self.bucket_bits), float(self.fb_tau), int(self.sub_bits), events,
+                        int(self.seg_pairs), 0)
 
 
 def plan(elem: int, n_elem: int, n_node: int, prec="fp64", tuning: Tuning | None = None, op="stiffness",
@@ -137,6 +139,7 @@ class LowerCSR:
         return int(self.status[1].item()) & 0xFFFFFFFF
 
     def to_torch(self) -> torch.Tensor:
+        """The matrix as ``torch.sparse_csr_tensor`` (int32 indices), sharing this CSR's memory."""
         n = self.row_ptr.numel() - 1
         return torch.sparse_csr_tensor(self.row_ptr, self.col_idx, self.vals, size=(n, n))
 
@@ -225,6 +228,14 @@ def build_lower_csr(conn, coords, coef, elem: int, prec="fp32fb64", tuning: Tuni
     return b.result(check=check, allow_flags=allow_flags)
 
 
+def lower_csr_tensor(conn, coords, coef, elem: int, prec="fp32fb64", tuning: Tuning | None = None,
+                     op="stiffness") -> torch.Tensor:
+    """Lower-triangular K as a ``torch.sparse_csr_tensor`` (int32 indices, trimmed to nnz,
+    values float64 for "fp64", float32 otherwise) on the mesh's device; raises
+    ``KBuildError`` on data errors."""
+    return build_lower_csr(conn, coords, coef, elem, prec=prec, tuning=tuning, op=op).to_torch()
+
+
 def assemble_lower_csr(conn, n_node: int, klow, elem: int, prec="fp64", tuning: Tuning | None = None, check=True,
                        allow_flags: int = 0, cap: int | None = None, dof: int = 1) -> LowerCSR:
     """Assemble lower CSR K from given per-element lower values klow [n_elem, nd(nd+1)/2],
@@ -287,6 +298,70 @@ class GroupedBuilder:
         _check(rc, "kb_build_lower_csr_grouped")
 
     result = Builder.result
+
+
+class StreamedGroupedBuilder:
+    """Grouped build (Eq. 10) of a mesh whose connectivity and coefficients stay in host
+    memory: only the group being built is on the device (the paper's upload of each
+    group's data, Section 3).  Each group is copied from pinned host memory on a copy
+    stream into one of two device staging buffers while the pass of the group before it
+    runs on the compute stream (``kb_build_lower_csr_group_pass``); the node coordinates
+    are device-resident.  The result equals ``GroupedBuilder``'s bit for bit.  ``run``
+    allocates nothing."""
+
+    def __init__(self, elem: int, n_elem: int, n_node: int, group_elems: int, cap: int, prec="fp32fb64",
+                 tuning: Tuning | None = None, device="cuda", op="stiffness"):
+        self.base = GroupedBuilder(elem, n_elem, n_node, group_elems, cap, prec, tuning, device, op)
+        b = self.base
+        self.n_groups = max(1, -(-b.n_elem // b.group)) if b.n_elem else 1
+        gmax = min(b.group, max(b.n_elem, 1))
+        dev = torch.device(device)
+        self.stage_conn = [torch.empty((gmax, b.elem), dtype=torch.int32, device=dev) for _ in range(2)]
+        self.stage_coef = [torch.empty(gmax, dtype=torch.float64, device=dev) for _ in range(2)]
+        self.copy_stream = torch.cuda.Stream(device=dev)  # default priority
+        self._free = [torch.cuda.Event(), torch.cuda.Event()]
+        self._up = [torch.cuda.Event(), torch.cuda.Event()]
+
+    def run(self, conn_host, coords, coef_host, stream=None):
+        """Enqueue every pass; ``conn_host`` [n_elem, nen] int32 and ``coef_host`` [n_elem]
+        float64 in pinned host memory, ``coords`` on the device."""
+        b = self.base
+        if conn_host.is_cuda or coef_host.is_cuda or not coords.is_cuda:
+            raise ValueError("conn and coef must be host tensors, coords a device tensor")
+        if not (conn_host.is_pinned() and coef_host.is_pinned()):
+            raise ValueError("conn and coef must be in pinned host memory (torch pin_memory)")
+        if conn_host.dtype != torch.int32 or conn_host.shape != (b.n_elem, b.elem) or not conn_host.is_contiguous():
+            raise ValueError(f"conn must be a contiguous int32 [{b.n_elem}, {b.elem}] tensor")
+        if coef_host.dtype != torch.float64 or coef_host.shape != (b.n_elem,) or not coef_host.is_contiguous():
+            raise ValueError(f"coef must be a contiguous float64 [{b.n_elem}] tensor")
+        if coords.dtype != torch.float64 or coords.shape != (b.n_node, 3) or not coords.is_contiguous():
+            raise ValueError(f"coords must be a contiguous float64 [{b.n_node}, 3] tensor")
+        compute = stream if stream is not None else torch.cuda.current_stream()
+        L = _lib.lib()
+        tu = b.tuning.to_c()
+        m = _mesh(b.elem, b.n_elem, b.n_node, None, coords, None, b.op)
+        for e in self._free:
+            e.record(compute)
+        for g in range(self.n_groups):
+            k = g % 2
+            e0 = g * b.group
+            e1 = min(b.n_elem, e0 + b.group)
+            with torch.cuda.stream(self.copy_stream):
+                self.copy_stream.wait_event(self._free[k])  # the pass two groups back is done with it
+                if e1 > e0:
+                    self.stage_conn[k][: e1 - e0].copy_(conn_host[e0:e1], non_blocking=True)
+                    self.stage_coef[k][: e1 - e0].copy_(coef_host[e0:e1], non_blocking=True)
+                self._up[k].record(self.copy_stream)
+            compute.wait_event(self._up[k])
+            rc = L.kb_build_lower_csr_group_pass(ctypes.byref(m), b.prec, ctypes.byref(tu), b.group, g,
+                                                 _ptr(self.stage_conn[k]), _ptr(self.stage_coef[k]), _ptr(b.ws),
+                                                 b.ws_bytes, _ptr(b.row_ptr), _ptr(b.col_idx), _ptr(b.vals), b.cap,
+                                                 _ptr(b.nnz_dev), _ptr(b.status), ctypes.c_void_p(compute.cuda_stream))
+            _check(rc, "kb_build_lower_csr_group_pass")
+            self._free[k].record(compute)
+
+    def result(self, check: bool = True, allow_flags: int = 0) -> LowerCSR:
+        return self.base.result(check=check, allow_flags=allow_flags)
 
 
 def build_lower_csr_grouped(conn, coords, coef, elem: int, group_elems: int, cap: int, prec="fp32fb64",
@@ -459,11 +534,20 @@ class BatchBuilder:
 
     ``run`` enqueues the whole batch on the current stream and allocates nothing, so it
     can be captured in a HIP graph (``torch.cuda.graph``) and replayed.
+
+    ``tuning="auto"`` takes the cached tuning for this batch's class of shapes, searched
+    (and cached) first if there is none (``tune_batch``).
     """
 
-    def __init__(self, batch: Batch, prec="fp32fb64", tuning: Tuning | None = None, cap: int | None = None):
+    def __init__(self, batch: Batch, prec="fp32fb64", tuning: Tuning | str | None = None, cap: int | None = None,
+                 tune_cache: str | None = None):
         self.batch = batch
         self.prec = _prec(prec)
+        self.tune_entry = None
+        if isinstance(tuning, str):
+            if tuning != "auto":
+                raise ValueError(f"tuning must be a Tuning, None or 'auto', not {tuning!r}")
+            tuning, self.tune_entry = tune_batch(batch, prec, cache_path=tune_cache)
         self.tuning = tuning or Tuning()
         n_elem, n_node = int(batch.conn.shape[0]), int(batch.coords.shape[0])
         self.ws_bytes, self.n_triplets = plan_batched(batch.elem, batch.n_mesh, n_elem, n_node, self.prec, self.tuning)
@@ -509,6 +593,21 @@ class BatchBuilder:
         return out
 
 
+def tune_batch(batch: Batch, prec="fp32fb64", cache_path: str | None = None, refresh: bool = False):
+    """(Tuning, cache entry) for this batch: the cached choice for its (architecture,
+    element, precision, size class), else a timed search over the tile, bucket, sub-bucket
+    and segment knobs, stored in the JSON cache (``autotune``)."""
+    from . import autotune
+
+    n_pairs = int(batch.conn.shape[0]) * batch.elem * (batch.elem + 1) // 2
+
+    def make_run(t):
+        b = BatchBuilder(batch, prec, t)
+        return b.run
+
+    return autotune.tuned("batch", batch.elem, prec, n_pairs, make_run, cache_path=cache_path, refresh=refresh)
+
+
 def build_lower_csr_batched(meshes, elem: int, prec="fp32fb64", tuning: Tuning | None = None, check=True,
                             allow_flags: int = 0, device="cuda") -> list:
     """Build each mesh of [(conn, coords, coef), ...] (mesh-local ids) in one batched call."""
@@ -517,48 +616,10 @@ def build_lower_csr_batched(meshes, elem: int, prec="fp32fb64", tuning: Tuning |
     return b.results(check=check, allow_flags=allow_flags)
 
 
-# ---- tuning search ---------------------------------------------------------------------
-def autotune(run_with, candidates, reps: int = 3, warmup: int = 1):
-    """Time ``run_with(tuning)`` (enqueues one build) for each candidate Tuning with HIP
-    events on the current stream; return (best tuning, {candidate: ms})."""
-    timings = {}
-    stream = torch.cuda.current_stream()
-    for t in candidates:
-        try:
-            for _ in range(warmup):
-                run_with(t)
-        except KBuildError:
-            continue  # not a valid configuration for this shape
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(reps):
-            run_with(t)
-        e1.record(stream)
-        e1.synchronize()
-        timings[t] = e0.elapsed_time(e1) / reps
-    if not timings:
-        raise KBuildError("no candidate tuning is valid for this shape")
-    best = min(timings, key=timings.get)
-    return best, timings
-
-
-def default_candidates(elem: int, prec="fp32fb64"):
-    """Tile size, first-level bucket width and sub-bucket width around the defaults."""
-    big = {(4, KB_FP64): 768, (8, KB_FP64): 192}.get((elem, _prec(prec)), 1024 if elem == 4 else 256)
-    small = big // 2 if (big // 2) % 64 == 0 else 64 * ((big // 2 + 63) // 64)
-    out = [Tuning()]
-    for blk in (big, small):
-        for bb in (0, 12, 14):
-            for sb in (0, 4, 5):
-                t = Tuning(block=blk, bucket_bits=bb, sub_bits=sb)
-                if t not in out:
-                    out.append(t)
-    return out
-
-
-__all__ = ["Builder", "BatchBuilder", "Batch", "LowerCSR", "KBuildError", "Tuning", "build_lower_csr",
+__all__ = ["Builder", "BatchBuilder", "Batch", "GroupedBuilder", "StreamedGroupedBuilder", "LowerCSR", "KBuildError", "Tuning", "build_lower_csr",
+           "lower_csr_tensor",
            "build_lower_csr_batched", "assemble_lower_csr", "integrate_lower", "adjoint_lower", "AdjointBuilder",
            "lower_csr_values",
            "pack_batch", "plan", "plan_batched",
-           "autotune", "default_candidates", "status_string", "version", "value_dtype", "STAGE_NAMES", "KB_N_STAGES",
+           "tune_batch", "status_string", "version", "value_dtype", "STAGE_NAMES", "KB_N_STAGES",
            "KB_HEX8", "KB_TET4", "KB_FP64", "KB_FP32", "KB_FP32_FB64", "KB_OP_STIFFNESS", "KB_OP_MASS"]

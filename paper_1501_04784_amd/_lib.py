@@ -18,7 +18,8 @@ STAGE_NAMES = ("init", "count", "offsets", "integrate", "histogram", "partition"
 
 # every function declared in include/kbuild.h
 EXPORTS = ("kb_plan", "kb_build_lower_csr", "kb_integrate_lower", "kb_assemble_lower_csr", "kb_plan_dof",
-           "kb_assemble_lower_csr_dof", "kb_plan_grouped", "kb_build_lower_csr_grouped", "kb_plan_batched", "kb_build_lower_csr_batched", "kb_plan_adjoint",
+           "kb_assemble_lower_csr_dof", "kb_plan_grouped", "kb_build_lower_csr_grouped",
+           "kb_build_lower_csr_group_pass", "kb_plan_batched", "kb_build_lower_csr_batched", "kb_plan_adjoint",
            "kb_adjoint_lower", "kb_status_string", "kb_version")
 
 
@@ -55,6 +56,8 @@ class KbTuning(ctypes.Structure):
         ("fb_tau", ctypes.c_float),
         ("sub_bits", ctypes.c_int32),
         ("stage_events", ctypes.c_void_p),
+        ("seg_pairs", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -88,6 +91,8 @@ def lib():
         L.kb_plan_grouped.restype = i32
         L.kb_build_lower_csr_grouped.argtypes = [PM, i32, PT, i64, p, sz, p, p, p, i64, p, p, p]
         L.kb_build_lower_csr_grouped.restype = i32
+        L.kb_build_lower_csr_group_pass.argtypes = [PM, i32, PT, i64, i64, p, p, p, sz, p, p, p, i64, p, p, p]
+        L.kb_build_lower_csr_group_pass.restype = i32
         PB = ctypes.POINTER(KbBatch)
         L.kb_plan_batched.argtypes = [PB, i32, PT, ctypes.POINTER(sz), ctypes.POINTER(i64)]
         L.kb_plan_batched.restype = i32

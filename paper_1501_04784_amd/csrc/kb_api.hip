@@ -31,6 +31,7 @@ constexpr int kSegThreads = 512;   // threads per pass-2 scatter workgroup
 constexpr int kTargetBuckets = 256;  // first-level buckets (pass-1 run length)
 constexpr double kSubEntries = 300;   // target distinct entries per sub-bucket
 constexpr int kHTMin = 512, kHTMax = 4096;
+constexpr int kHeavyGrid = 64;  // workgroups of k_pass3_heavy (each takes whole sub-buckets)
 constexpr double kHalfTileRatio = 16;   // pairs per tile x bucket histogram entry
 constexpr size_t kWideStage = 112640;  // staged pair bytes per pass-1 tile, elements of > 8 rows
 
@@ -56,7 +57,7 @@ struct Plan {
   size_t lds1 = 0, lds2 = 0;
   // workspace offsets
   size_t o_coords4 = 0, o_hist = 0, o_csum = 0, o_tot = 0, o_part = 0, o_total = 0, o_bstart = 0, o_segbase = 0, o_hist2 = 0, o_seg2b = 0, o_emax = 0,
-         o_dconn = 0, o_tres = 0, o_row1 = 0, o_col1 = 0, o_val1 = 0, o_key2 = 0, o_val2 = 0, o_sbb = 0, o_rowoff = 0, o_usub = 0, o_ubase = 0,
+         o_dconn = 0, o_ovl = 0, o_tres = 0, o_row1 = 0, o_col1 = 0, o_val1 = 0, o_key2 = 0, o_val2 = 0, o_sbb = 0, o_rowoff = 0, o_usub = 0, o_ubase = 0,
          total = 0;
 };
 
@@ -123,6 +124,8 @@ int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p, int dof 
     if (tu->bucket_bits && tu->sub_bits && tu->sub_bits > tu->bucket_bits) return KB_EINVAL;
     bucket_bits = tu->bucket_bits;
     sub_bits = tu->sub_bits;
+    if ((tu->seg_pairs != 0 && tu->seg_pairs != kSeg && tu->seg_pairs != kSegLong) || tu->reserved != 0)
+      return KB_EINVAL;
   }
   // sub-buckets: about a third of the pass-3 hash table of distinct entries on average;
   // distinct entries per row estimated from the pairs per row and the typical number
@@ -155,6 +158,27 @@ int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p, int dof 
     p->s1 = std::min(16, p->s2 + d);
   }
   if (p->s1 - p->s2 > 10) return KB_EINVAL;
+  // pass-1 staging per tile (bytes): the smallest tile the plan may take, and the scan words
+  const size_t wide_tile = std::min<size_t>(256, std::max<size_t>(1, kWideStage / ((size_t)p->te * (8 + p->vbytes))));
+  const size_t stage_min = p->nen <= 8 ? (size_t)(p->nen == 4 ? (prec == KB_FP64 ? 384 : 512) : 128) * p->te *
+                                                 (8 + p->vbytes) + 4 * (2 * 512 / 64 + 2)
+                                       : wide_tile * p->te * (8 + p->vbytes) + 4 * (kWideThreads / 64 + 2) +
+                                             wide_tile * ((size_t)p->nen * 12 + 4) + 2 * (size_t)p->te;
+  if (!bucket_bits && !sub_bits) {
+    // very many rows: pass 1 keeps two LDS counters per bucket beside its staged pairs;
+    // widen the buckets (beyond 1024 sub-buckets per bucket, the sub-buckets too) until
+    // they fit beside the smallest tile
+    // (the sub-bucket key packs the row within its sub-bucket beside the column in 31
+    // bits, so the sub-buckets widen only up to s2_max: about 1.3e8 rows at most)
+    while (p->s1 < 16 && stage_min + 8 * (size_t)div_up(p->nn, (int64_t)1 << p->s1) > 163840) {
+      if (p->s1 + 1 - p->s2 > 10) {
+        if (p->s2 + 1 > s2_max) break;
+        ++p->s2;
+        while (p->ht < kHTMax && p->ht < 4.0 * (double)(1 << p->s2) * u_row) p->ht *= 2;
+      }
+      ++p->s1;
+    }
+  }
   p->p2 = 1 << (p->s1 - p->s2);
   p->nb = (int)div_up(p->nn, (int64_t)1 << p->s1);
   p->nsub = (int64_t)p->nb * p->p2;
@@ -183,9 +207,10 @@ int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p, int dof 
       p->tile = small;
     if (tu && (tu->block == big || tu->block == small || (mid && tu->block == mid))) p->tile = tu->block;
     if (mid && p->tile == big && lds_of(big) > 163840) p->tile = mid;
+    if (lds_of(p->tile) > 163840) p->tile = small;  // many buckets: the counters need the room
     p->lds1 = lds_of(p->tile);
   } else {
-    p->tile = (int)std::min<size_t>(256, std::max<size_t>(1, kWideStage / ((size_t)p->te * (8 + p->vbytes))));
+    p->tile = (int)wide_tile;
     p->lds1 = (size_t)p->tile * p->te * (8 + p->vbytes) + 2 * 4 * (size_t)p->nb + 4 * (kWideThreads / 64 + 2) +
               (size_t)p->tile * p->nen * 12 + 4 * (size_t)p->tile + 2 * (size_t)p->te;
   }
@@ -194,7 +219,10 @@ int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p, int dof 
   p->nhist = (int64_t)p->nb * (p->ntiles + p->ntiles_csr);
   if (csr_cap > 0 && 2 * (size_t)kCsrTile * (8 + p->vbytes) + 2 * 4 * (size_t)p->nb + 4 * (256 / 64 + 2) > 163840)
     return KB_EINVAL;
-  p->seg = (m->elem == KB_TET4 && (int64_t)kSeg < (int64_t)kMinRun * p->p2) ? kSegLong : kSeg;
+  if (tu && tu->seg_pairs)
+    p->seg = tu->seg_pairs;
+  else
+    p->seg = (m->elem == KB_TET4 && (int64_t)kSeg < (int64_t)kMinRun * p->p2) ? kSegLong : kSeg;
   p->nseg_max = div_up(p->T, p->seg) + p->nb;
   p->lds2 = (size_t)p->seg * (p->vbytes + 4 + 2) + 2 * 4 * (size_t)p->p2 + 4 * (kSegThreads / 64 + 1);
   if (p->lds1 > 163840 || p->lds2 > 163840) return KB_EINVAL;
@@ -217,7 +245,8 @@ int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p, int dof 
   p->o_segbase = take(4 * ((size_t)p->nb + 1));
   p->o_hist2 = take(4 * (size_t)(p->nseg_max * p->p2));
   p->o_seg2b = take(4 * (size_t)p->nseg_max);
-  p->o_emax = take(4);
+  p->o_emax = take(8);  // largest value exponent, then the count of heavy sub-buckets
+  p->o_ovl = take(4 * (size_t)p->nsub);  // heavy sub-buckets (k_pass3_heavy)
   p->o_dconn = take(p->dof > 1 ? 4 * (size_t)p->nen * (size_t)p->nel : 0);  // expanded connectivity
   p->o_tres = take(csr_cap > 0 ? p->vbytes * T : 0);  // residuals of the reduced entries
   p->o_row1 = take(2 * T);
@@ -371,28 +400,39 @@ struct Carry {
   int32_t* rows_out = nullptr;
 };
 
+// pass 3, then the sub-buckets it could not hold (k_pass3_heavy: a small grid whose
+// workgroups return at once when there are none)
 template <typename V, bool RES>
-void launch_pass3(const Plan& p, uint32_t* key2, V* val2, uint32_t* sbb, uint32_t* emax, int32_t* tcol, V* tval,
-                  V* tres, uint32_t* rowoff, uint32_t* usub, hipStream_t s) {
+int launch_pass3(const Plan& p, uint32_t* key2, V* val2, uint32_t* sbb, uint32_t* emax, int32_t* tcol, V* tval,
+                 V* tres, uint32_t* rowoff, uint32_t* usub, uint32_t* ov_list, hipStream_t s) {
   const unsigned g3 = (unsigned)p.nsub;
+  uint32_t* ov_count = emax + 1;
   switch (p.ht) {
     case 512:
       k_pass3<V, 512, RES><<<g3, 256, 0, s>>>(key2, val2, sbb, p.s2, p.colbits, p.nn, emax, tcol, tval, tres, rowoff,
-                                              usub);
+                                              usub, ov_list, ov_count);
       break;
     case 1024:
       k_pass3<V, 1024, RES><<<g3, 256, 0, s>>>(key2, val2, sbb, p.s2, p.colbits, p.nn, emax, tcol, tval, tres,
-                                               rowoff, usub);
+                                               rowoff, usub, ov_list, ov_count);
       break;
     case 2048:
       k_pass3<V, 2048, RES><<<g3, 256, 0, s>>>(key2, val2, sbb, p.s2, p.colbits, p.nn, emax, tcol, tval, tres,
-                                               rowoff, usub);
+                                               rowoff, usub, ov_list, ov_count);
       break;
     default:
       k_pass3<V, 4096, RES><<<g3, 256, 0, s>>>(key2, val2, sbb, p.s2, p.colbits, p.nn, emax, tcol, tval, tres,
-                                               rowoff, usub);
+                                               rowoff, usub, ov_list, ov_count);
       break;
   }
+  KB_LAUNCH_CHECK();
+  auto kh = k_pass3_heavy<V, RES>;
+  if (!set_lds(kh, HeavySmem::bytes())) return KB_EHIP;
+  const unsigned gh = (unsigned)std::min<int64_t>(p.nsub, kHeavyGrid);
+  kh<<<gh, kHeavyThreads, HeavySmem::bytes(), s>>>(key2, val2, (uint32_t*)tcol, tval, sbb, p.s2, p.colbits, p.nn, emax,
+                                                   tres, rowoff, usub, ov_list, ov_count);
+  KB_LAUNCH_CHECK();
+  return KB_OK;
 }
 
 template <typename V>
@@ -441,11 +481,11 @@ int assemble_tail(const Plan& p, unsigned char* ws, int32_t* row_ptr, int32_t* c
   auto* tres = (V*)(ws + p.o_tres);
   KB_TRY(ev.rec(KB_STAGE_REDUCE));
   if (p.nsub > 0) {
+    auto* ov_list = (uint32_t*)(ws + p.o_ovl);
     if (cr)
-      launch_pass3<V, true>(p, key2, val2, sbb, emax, tcol, tval, tres, rowoff, usub, s);
+      KB_TRY((launch_pass3<V, true>(p, key2, val2, sbb, emax, tcol, tval, tres, rowoff, usub, ov_list, s)));
     else
-      launch_pass3<V, false>(p, key2, val2, sbb, emax, tcol, tval, nullptr, rowoff, usub, s);
-    KB_LAUNCH_CHECK();
+      KB_TRY((launch_pass3<V, false>(p, key2, val2, sbb, emax, tcol, tval, nullptr, rowoff, usub, ov_list, s)));
   }
   KB_TRY(ev.rec(KB_STAGE_COMPRESS));
   KB_TRY(scan((const int32_t*)usub, p.nsub, part, (int32_t*)ubase, nnz_dev, s));
@@ -487,7 +527,7 @@ int build_impl(const Plan& p, const kb_mesh* m, const void* klow, unsigned char*
     k_init_status<<<1, 64, 0, s>>>(status, nnz_dev);
     KB_LAUNCH_CHECK();
   }
-  k_fill_i32<<<1, 64, 0, s>>>((int32_t*)(ws + p.o_emax), 1, 0);
+  k_fill_i32<<<1, 64, 0, s>>>((int32_t*)(ws + p.o_emax), 2, 0);
   KB_LAUNCH_CHECK();
 
   KB_TRY(ev.rec(KB_STAGE_COUNT));
@@ -805,22 +845,15 @@ int kb_plan_grouped(const kb_mesh* mesh, int prec, const kb_tuning* tuning, int6
   return KB_OK;
 }
 
-int kb_build_lower_csr_grouped(const kb_mesh* mesh, int prec, const kb_tuning* tuning, int64_t group_elems, void* ws,
-                               size_t ws_bytes, int32_t* row_ptr, int32_t* col_idx, void* vals, int64_t cap,
-                               int64_t* nnz_dev, uint32_t* status_dev, void* stream) {
-  GroupPlan gp;
-  KB_TRY(make_group_plan(mesh, prec, tuning, group_elems, cap, &gp));
-  KB_TRY(check_mesh_ptrs(mesh, true));
-  if (!row_ptr || !nnz_dev || !status_dev) return KB_EINVAL;
-  if (cap > 0 && (!col_idx || !vals)) return KB_EINVAL;
-  if (ws_bytes < gp.total) return KB_ENOSPC;
-  if (!ws) return KB_EINVAL;
-  KB_TRY(device_cus(&gp.p.cus));
-  auto* w = (unsigned char*)ws;
-  auto s = (hipStream_t)stream;
+// One pass g of a grouped build: group g's elements (conn_g, coef_g: its n_elem rows)
+// integrated and assembled together with the running sums of the passes before it.
+// The two sets of running sums alternate (A = the caller's arrays, B = workspace) so
+// that the last pass writes the caller's arrays.
+static int grouped_pass(const GroupPlan& gp, const kb_mesh* mesh, int64_t g, const int32_t* conn_g,
+                        const double* coef_g, unsigned char* w, int32_t* row_ptr, int32_t* col_idx, void* vals,
+                        int64_t cap, int64_t* nnz_dev, uint32_t* status_dev, const kb_tuning* tuning, hipStream_t s) {
   Events none{nullptr, s};
   Events ev{tuning ? tuning->stage_events : nullptr, s};
-  // the two sets of running sums: A = the caller's arrays, B = workspace
   struct Set {
     int32_t* rp;
     int32_t* col;
@@ -832,40 +865,73 @@ int kb_build_lower_csr_grouped(const kb_mesh* mesh, int prec, const kb_tuning* t
   const Set A{row_ptr, col_idx, vals, w + gp.o_resA, (int32_t*)(w + gp.o_rowsA), nnz_dev};
   const Set B{(int32_t*)(w + gp.o_rpB), (int32_t*)(w + gp.o_colB), w + gp.o_valB, w + gp.o_resB,
               (int32_t*)(w + gp.o_rowsB), (int64_t*)(w + gp.o_nnzB)};
+  kb_mesh mg = *mesh;  // this group's elements as a mesh; all nodes
+  const int64_t e0 = g * gp.group;
+  mg.n_elem = std::max<int64_t>(0, std::min<int64_t>(gp.group, mesh->n_elem - e0));
+  mg.conn = conn_g;
+  mg.coef = coef_g;
+  Plan p = gp.p;
+  p.nel = mg.n_elem;
+  p.ntiles = div_up(p.nel, p.tile);
+  const Set& out = ((gp.n_groups - 1 - g) % 2 == 0) ? A : B;
+  const Set& in = (&out == &A) ? B : A;
+  Carry cr;
+  cr.first = g == 0;
+  if (g > 0) {
+    cr.rows = in.rows;
+    cr.cols = in.col;
+    cr.vals = in.val;
+    cr.res = in.res;
+    cr.nnz = in.nnz;
+  }
+  cr.res_out = out.res;
+  cr.rows_out = out.rows;
+  const Carry* crp = gp.n_groups > 1 ? &cr : nullptr;
+  Events& e = g == gp.n_groups - 1 ? ev : none;
+  if (p.nen == 8) return dispatch_build<8>(p, &mg, nullptr, w, out.rp, out.col, out.val, cap, out.nnz, status_dev, e, s, crp);
+  return dispatch_build<4>(p, &mg, nullptr, w, out.rp, out.col, out.val, cap, out.nnz, status_dev, e, s, crp);
+}
+
+static int check_grouped_args(const GroupPlan& gp, int32_t* row_ptr, int32_t* col_idx, void* vals, int64_t cap,
+                              int64_t* nnz_dev, uint32_t* status_dev, void* ws, size_t ws_bytes) {
+  if (!row_ptr || !nnz_dev || !status_dev) return KB_EINVAL;
+  if (cap > 0 && (!col_idx || !vals)) return KB_EINVAL;
+  if (ws_bytes < gp.total) return KB_ENOSPC;
+  if (!ws) return KB_EINVAL;
+  return KB_OK;
+}
+
+int kb_build_lower_csr_grouped(const kb_mesh* mesh, int prec, const kb_tuning* tuning, int64_t group_elems, void* ws,
+                               size_t ws_bytes, int32_t* row_ptr, int32_t* col_idx, void* vals, int64_t cap,
+                               int64_t* nnz_dev, uint32_t* status_dev, void* stream) {
+  GroupPlan gp;
+  KB_TRY(make_group_plan(mesh, prec, tuning, group_elems, cap, &gp));
+  KB_TRY(check_mesh_ptrs(mesh, true));
+  KB_TRY(check_grouped_args(gp, row_ptr, col_idx, vals, cap, nnz_dev, status_dev, ws, ws_bytes));
+  KB_TRY(device_cus(&gp.p.cus));
   for (int64_t g = 0; g < gp.n_groups; ++g) {
-    // this group's elements as a mesh; all nodes
-    kb_mesh mg = *mesh;
     const int64_t e0 = g * gp.group;
-    mg.n_elem = std::min<int64_t>(gp.group, mesh->n_elem - e0);
-    if (mg.n_elem < 0) mg.n_elem = 0;
-    if (mesh->n_elem > 0) {
-      mg.conn = mesh->conn + e0 * mesh->elem;
-      mg.coef = mesh->coef + e0;
-    }
-    Plan p = gp.p;
-    p.nel = mg.n_elem;
-    p.ntiles = div_up(p.nel, p.tile);
-    const Set& out = ((gp.n_groups - 1 - g) % 2 == 0) ? A : B;
-    const Set& in = (&out == &A) ? B : A;
-    Carry cr;
-    cr.first = g == 0;
-    if (g > 0) {
-      cr.rows = in.rows;
-      cr.cols = in.col;
-      cr.vals = in.val;
-      cr.res = in.res;
-      cr.nnz = in.nnz;
-    }
-    cr.res_out = out.res;
-    cr.rows_out = out.rows;
-    const Carry* crp = gp.n_groups > 1 ? &cr : nullptr;
-    Events& e = g == gp.n_groups - 1 ? ev : none;
-    if (p.nen == 8)
-      KB_TRY(dispatch_build<8>(p, &mg, nullptr, w, out.rp, out.col, out.val, cap, out.nnz, status_dev, e, s, crp));
-    else
-      KB_TRY(dispatch_build<4>(p, &mg, nullptr, w, out.rp, out.col, out.val, cap, out.nnz, status_dev, e, s, crp));
+    const int32_t* cg = mesh->n_elem > 0 ? mesh->conn + e0 * mesh->elem : nullptr;
+    const double* fg = mesh->n_elem > 0 ? mesh->coef + e0 : nullptr;
+    KB_TRY(grouped_pass(gp, mesh, g, cg, fg, (unsigned char*)ws, row_ptr, col_idx, vals, cap, nnz_dev, status_dev,
+                        tuning, (hipStream_t)stream));
   }
   return KB_OK;
+}
+
+int kb_build_lower_csr_group_pass(const kb_mesh* mesh, int prec, const kb_tuning* tuning, int64_t group_elems,
+                                  int64_t group, const int32_t* group_conn, const double* group_coef, void* ws,
+                                  size_t ws_bytes, int32_t* row_ptr, int32_t* col_idx, void* vals, int64_t cap,
+                                  int64_t* nnz_dev, uint32_t* status_dev, void* stream) {
+  GroupPlan gp;
+  KB_TRY(make_group_plan(mesh, prec, tuning, group_elems, cap, &gp));
+  if (group < 0 || group >= gp.n_groups) return KB_EINVAL;
+  const int64_t ng = std::max<int64_t>(0, std::min<int64_t>(gp.group, mesh->n_elem - group * gp.group));
+  if (ng > 0 && (!group_conn || !group_coef || !mesh->coords)) return KB_EINVAL;
+  KB_TRY(check_grouped_args(gp, row_ptr, col_idx, vals, cap, nnz_dev, status_dev, ws, ws_bytes));
+  KB_TRY(device_cus(&gp.p.cus));
+  return grouped_pass(gp, mesh, group, group_conn, group_coef, (unsigned char*)ws, row_ptr, col_idx, vals, cap,
+                      nnz_dev, status_dev, tuning, (hipStream_t)stream);
 }
 
 int kb_plan_batched(const kb_batch* batch, int prec, const kb_tuning* tuning, size_t* ws_bytes,

@@ -1022,70 +1022,11 @@ __device__ __forceinline__ uint32_t slot_hash(uint32_t k) {
   return k >> (32 - bits);
 }
 
-// single-lane path for a sub-bucket whose distinct entries overflow the table: heap
-// sort the pairs in place by key, then exact sums of equal keys (same result as the
-// LDS path, which uses the same exact arithmetic).
-template <typename V, bool RES>
-__device__ void pass3_global(uint32_t* key, V* val, int64_t n, int64_t r0, int R, int colbits, int F, int32_t* tcol,
-                             V* tval, V* tres, uint32_t* rowoff, uint32_t* usub) {
-  auto sift = [&](int64_t root, int64_t end) {
-    while (true) {
-      int64_t child = 2 * root + 1;
-      if (child >= end) break;
-      if (child + 1 < end && key[child] < key[child + 1]) ++child;
-      if (!(key[root] < key[child])) break;
-      const uint32_t tk = key[root];
-      key[root] = key[child];
-      key[child] = tk;
-      const V tv = val[root];
-      val[root] = val[child];
-      val[child] = tv;
-      root = child;
-    }
-  };
-  for (int64_t s = n / 2 - 1; s >= 0; --s) sift(s, n);
-  for (int64_t end = n - 1; end > 0; --end) {
-    const uint32_t tk = key[0];
-    key[0] = key[end];
-    key[end] = tk;
-    const V tv = val[0];
-    val[0] = val[end];
-    val[end] = tv;
-    sift(0, end);
-  }
-  for (int r = 0; r < R; ++r) rowoff[r0 + r] = 0;  // counts first, offsets below
-  const uint32_t cmask = (1u << colbits) - 1;
-  int64_t u = 0, q = 0;
-  while (q < n) {
-    const uint32_t k0 = key[q];
-    uint64_t lo = 0, hi = 0;
-    while (q < n && key[q] == k0) {
-      uint64_t a, b;
-      to_fixed((double)val[q], F, a, b);
-      const uint64_t s = lo + a;
-      hi += b + (s < lo ? 1ull : 0ull);
-      lo = s;
-      ++q;
-    }
-    tcol[u] = (int32_t)(k0 & cmask);
-    const V h = from_fixed_as<V>(lo, hi, F);
-    tval[u] = h;
-    if constexpr (RES) tres[u] = fixed_residual<V>(lo, hi, F, h);
-    rowoff[r0 + (k0 >> colbits)] += 1;
-    ++u;
-  }
-  uint32_t run = 0;
-  for (int r = 0; r < R; ++r) {
-    const uint32_t c = rowoff[r0 + r];
-    rowoff[r0 + r] = run;
-    run += c;
-  }
-  *usub = (uint32_t)u;
-}
-
 // One workgroup per sub-bucket g (rows [g << s2, ...)).  Writes its unique entries in
 // CSR order to tcol/tval[sbb[g] + f], each row's first entry (relative to the
-// sub-bucket) to rowoff, its total to usub[g].
+// sub-bucket) to rowoff, its total to usub[g].  A sub-bucket of more than 2^16 pairs
+// or more distinct entries than the table holds is appended to ov_list (count in
+// *ov_count) and left to k_pass3_heavy.
 // Sub-buckets run in their natural order: under a random numbering the lower-triangle
 // pairs of a row grow with its id, so an even interleave keeps the XCDs balanced.
 // With RES, each entry's residual (the exact sum minus its rounding) goes to tres too.
@@ -1094,7 +1035,8 @@ __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* _
                                                const uint32_t* __restrict__ sbb, int s2, int colbits, int64_t n_node,
                                                const uint32_t* __restrict__ emax, int32_t* __restrict__ tcol,
                                                V* __restrict__ tval, V* __restrict__ tres,
-                                               uint32_t* __restrict__ rowoff, uint32_t* __restrict__ usub) {
+                                               uint32_t* __restrict__ rowoff, uint32_t* __restrict__ usub,
+                                               uint32_t* __restrict__ ov_list, uint32_t* __restrict__ ov_count) {
   constexpr int NT = 256, PER = 8;
   // once summed, each slot's value (and residual) is kept in place of its low chunk sum,
   // which frees the high chunk sums for the columns grouped by row (one array fewer, six
@@ -1125,7 +1067,7 @@ __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* _
     s_hi[h] = 0ull;
   }
   for (int r = threadIdx.x; r < (1 << s2); r += NT) s_rc[r] = 0;
-  // more than 2^16 pairs could overflow the chunk sums: take the global path
+  // more than 2^16 pairs could overflow the chunk sums: left to the heavy kernel
   if (threadIdx.x == 0) {
     s_over = (end - beg > (1u << 16)) ? 1u : 0u;
     s_nu = 0;
@@ -1189,10 +1131,8 @@ __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* _
     }
   }
   __syncthreads();
-  if (s_over) {
-    if (threadIdx.x == 0)
-      pass3_global<V, RES>(ikey + beg, ival + beg, end - beg, r0, R, colbits, F, tcol + beg, tval + beg,
-                           RES ? tres + beg : nullptr, rowoff, usub + g);
+  if (s_over) {  // left to k_pass3_heavy
+    if (threadIdx.x == 0) ov_list[atomicAdd(ov_count, 1u)] = (uint32_t)g;
     return;
   }
   // order the U entries by (row, col): the row counts (taken at insertion) scanned by one
@@ -1263,6 +1203,329 @@ __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* _
   }
   for (int r = threadIdx.x; r < R; r += NT) rowoff[r0 + r] = s_ro[r];
   if (threadIdx.x == 0) usub[g] = U;
+}
+
+// ------------------------------------------------------------ heavy sub-buckets
+// A sub-bucket that overflows pass 3 (a node shared by very many elements: its row holds
+// more distinct entries than an LDS table, or more than 2^16 pairs) is reduced by one
+// 1024-lane workgroup, which splits it by key into ranges of at most kLeafKeys keys:
+//   - the key range [kmin, kmax] of the sub-bucket; a range wider than kLeafKeys is split
+//     into at most 1024 digit ranges of 2^shift keys (a histogram, its scan and a
+//     scatter into the other buffer, at the same place), twice at most for 31-bit keys;
+//   - each leaf range (in key order) sums its pairs into a direct-addressed LDS table,
+//     one slot per key, with the exact chunk sums of pass 3, carried into a third word
+//     after every 2^16 pairs (so any number of pairs sums exactly); then the occupied
+//     slots, in slot order = (row, col) order, are written after the entries before.
+// Output as pass 3.  The pairs alternate between (ikey, ival) and (akey, aval), the
+// pass-1 arrays, which also receive the output (tcol / tval): a leaf writes at most as
+// many entries as it has pairs, so the output never reaches a pair not yet read.
+constexpr int kLeafKeys = 4096, kHeavyThreads = 1024, kDigits = 1024;
+
+struct HeavySmem {
+  unsigned long long* lo;  // [kLeafKeys] sum of low 48-bit chunks
+  long long* hi;           // [kLeafKeys] sum of signed high chunks (bits 48..)
+  long long* top;          // [kLeafKeys] carries above bit 96
+  uint32_t* occ;           // [kLeafKeys / 32] occupied slots
+  uint32_t* hist;          // [kDigits] digit counts, then cursors
+  uint32_t* start;         // [2][kDigits + 1] digit starts of the two split levels
+  uint32_t* rowcnt;        // [256] entries per row of the sub-bucket
+  uint32_t* scan;          // [kHeavyThreads / 64 + 1]
+  uint32_t* misc;          // [4]
+  __device__ explicit HeavySmem(unsigned char* p) {
+    lo = (unsigned long long*)p;
+    hi = (long long*)(lo + kLeafKeys);
+    top = hi + kLeafKeys;
+    occ = (uint32_t*)(top + kLeafKeys);
+    hist = occ + kLeafKeys / 32;
+    start = hist + kDigits;
+    rowcnt = start + 2 * (kDigits + 1);
+    scan = rowcnt + 256;
+    misc = scan + kHeavyThreads / 64 + 1;
+  }
+  static constexpr size_t bytes() {
+    return (size_t)kLeafKeys * 24 + 4 * ((size_t)kLeafKeys / 32 + kDigits + 2 * (kDigits + 1) + 256 +
+                                         kHeavyThreads / 64 + 1 + 4);
+  }
+};
+
+// block-wide barrier after global stores that other waves of the workgroup read next:
+// the barrier's workgroup-scope fence waits for the stores, and the waves of one
+// workgroup share the compute unit's write-through vector cache (an agent-scope fence
+// here would write back and invalidate the whole L2 at every call)
+__device__ __forceinline__ void heavy_sync() { __syncthreads(); }
+
+// Stream [a, b) of (key, value) pairs through f(key, value, ok), kHeavyPer pairs per lane
+// in flight (indices clamped into the range; the empty asm keeps the loads ahead of the
+// atomics that use them).  f is called by every lane in uniform control flow, ok telling
+// whether its pair is in the range, so that f can combine the lanes of a wave.
+// WITH_VAL = false reads the keys only.
+constexpr int kHeavyPer = 8;
+template <bool WITH_VAL, typename V, typename Fn>
+__device__ __forceinline__ void heavy_stream(const uint32_t* key, const V* val, uint32_t a, uint32_t b, Fn f) {
+  for (uint32_t i0 = a; i0 < b; i0 += kHeavyPer * kHeavyThreads) {
+    uint32_t kk[kHeavyPer];
+    V vv[kHeavyPer] = {};
+#pragma unroll
+    for (int u = 0; u < kHeavyPer; ++u) {
+      const uint32_t i = i0 + u * kHeavyThreads + threadIdx.x;
+      const uint32_t ic = i < b ? i : a;
+      kk[u] = key[ic];
+      if constexpr (WITH_VAL) vv[u] = val[ic];
+    }
+#pragma unroll
+    for (int u = 0; u < kHeavyPer; ++u) {
+      if constexpr (WITH_VAL)
+        asm volatile("" : "+v"(kk[u]), "+v"(vv[u]));
+      else
+        asm volatile("" : "+v"(kk[u]));
+    }
+#pragma unroll
+    for (int u = 0; u < kHeavyPer; ++u) f(kk[u], vv[u], i0 + u * kHeavyThreads + threadIdx.x < b);
+  }
+}
+
+// A heavy node's diagonal (or one column of its row) can own most pairs of a range, and
+// atomics on one LDS address serialise.  Each wave therefore takes its first lane's
+// digit or slot as "hot": when more than one lane holds it, those lanes are combined into
+// one atomic by the first lane (heavy_hot returns their mask, else 0).
+__device__ __forceinline__ uint64_t heavy_hot(uint32_t x, bool ok, uint32_t& hot) {
+  hot = __builtin_amdgcn_readfirstlane(x);
+  const uint64_t m = __ballot(ok && x == hot);
+  return __popcll(m) > 1 ? m : 0ull;
+}
+
+template <typename V>
+__device__ void heavy_split(const HeavySmem& sm, const uint32_t* skey, const V* sval, uint32_t* dkey, V* dval,
+                            uint32_t a, uint32_t b, uint32_t kmin, int shift, int nd, uint32_t* st) {
+  const int lane = threadIdx.x & 63;
+  for (int d = threadIdx.x; d < nd; d += kHeavyThreads) sm.hist[d] = 0;
+  __syncthreads();
+  heavy_stream<false>(skey, sval, a, b, [&](uint32_t k, V, bool ok) {
+    const uint32_t d = (k - kmin) >> shift;
+    uint32_t hot;
+    const uint64_t m = heavy_hot(d, ok, hot);
+    if (ok && !((m >> lane) & 1ull)) atomicAdd(&sm.hist[d], 1u);
+    if (lane == 0 && m) atomicAdd(&sm.hist[hot], (uint32_t)__popcll(m));
+  });
+  __syncthreads();
+  block_scan_array(sm.hist, nd, sm.scan);  // (ends with a barrier)
+  for (int d = threadIdx.x; d < nd; d += kHeavyThreads) st[d] = a + sm.hist[d];
+  if (threadIdx.x == 0) st[nd] = b;
+  __syncthreads();
+  heavy_stream<true>(skey, sval, a, b, [&](uint32_t k, V v, bool ok) {
+    const uint32_t d = (k - kmin) >> shift;
+    uint32_t hot;
+    const uint64_t m = heavy_hot(d, ok, hot);
+    uint32_t base = 0;
+    if (lane == 0 && m) base = atomicAdd(&sm.hist[hot], (uint32_t)__popcll(m));
+    base = __shfl(base, 0, 64);
+    const bool mine = (m >> lane) & 1ull;
+    uint32_t pos = 0;
+    if (mine)
+      pos = a + base + (uint32_t)__popcll(m & ((1ull << lane) - 1));
+    else if (ok)
+      pos = a + atomicAdd(&sm.hist[d], 1u);
+    if (ok) {
+      dkey[pos] = k;
+      dval[pos] = v;
+    }
+  });
+  heavy_sync();
+}
+
+// carry the low and high chunk sums of the occupied slots upward: lo < 2^48, hi < 2^48
+__device__ __forceinline__ void heavy_normalise(const HeavySmem& sm) {
+  constexpr unsigned long long M48 = (1ull << 48) - 1;
+  for (int h = threadIdx.x; h < kLeafKeys; h += kHeavyThreads) {
+    if (!((sm.occ[h >> 5] >> (h & 31)) & 1u)) continue;
+    const unsigned long long l = sm.lo[h];
+    const long long x = sm.hi[h] + (long long)(l >> 48);
+    sm.lo[h] = l & M48;
+    sm.top[h] += x >> 48;  // arithmetic shift: floor division
+    sm.hi[h] = (long long)((unsigned long long)x & M48);
+  }
+}
+
+// sums of the leaf's pairs [a, b) (keys in [kmin, kmin + kLeafKeys)), appended in key
+// order at tcol / tval [u0 ...); returns the number of entries
+template <typename V, bool RES>
+__device__ uint32_t heavy_leaf(const HeavySmem& sm, const uint32_t* key, const V* val, uint32_t a, uint32_t b,
+                               uint32_t kmin, int F, int colbits, int32_t* tcol, V* tval, V* tres, uint32_t u0) {
+  // pairs per round: the carried sums (below 2^48) plus kRound chunks (below 2^48
+  // unsigned, below 2^47 in magnitude signed) stay inside 64 bits
+  constexpr uint32_t kRound = 65532;
+  const int lane = threadIdx.x & 63;
+  for (uint32_t r = a; r < b; r += kRound) {
+    const uint32_t re = b - r > kRound ? r + kRound : b;
+    heavy_stream<true>(key, val, r, re, [&](uint32_t k, V v, bool ok) {
+      const uint32_t h = k - kmin;
+      uint64_t c0;
+      int64_t c1;
+      to_chunks(v, F, c0, c1);
+      uint32_t hot;
+      const uint64_t m = heavy_hot(h, ok, hot);
+      if (ok && !((m >> lane) & 1ull)) {
+        atomicAdd(&sm.lo[h], (unsigned long long)c0);
+        atomicAdd((unsigned long long*)&sm.hi[h], (unsigned long long)c1);
+        atomicOr(&sm.occ[h >> 5], 1u << (h & 31));
+      }
+      if (m) {  // the hot lanes' chunks summed over the wave (64 chunks stay below 2^54)
+        unsigned long long s0 = ((m >> lane) & 1ull) ? c0 : 0ull;
+        long long s1 = ((m >> lane) & 1ull) ? c1 : 0ll;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+          s0 += __shfl_xor(s0, o, 64);
+          s1 += __shfl_xor(s1, o, 64);
+        }
+        if (lane == 0) {
+          atomicAdd(&sm.lo[hot], s0);
+          atomicAdd((unsigned long long*)&sm.hi[hot], (unsigned long long)s1);
+          atomicOr(&sm.occ[hot >> 5], 1u << (hot & 31));
+        }
+      }
+    });
+    __syncthreads();
+    heavy_normalise(sm);
+    __syncthreads();
+  }
+  // the occupied slots in order: kLeafKeys / kHeavyThreads consecutive slots per lane
+  constexpr int PL = kLeafKeys / kHeavyThreads;
+  const int h0 = threadIdx.x * PL;
+  const uint32_t bits = (sm.occ[h0 >> 5] >> (h0 & 31)) & ((1u << PL) - 1);
+  uint32_t total;
+  uint32_t pos = u0 + block_scan_u32(__popc(bits), sm.scan, &total);
+  const uint32_t cmask = (1u << colbits) - 1;
+#pragma unroll
+  for (int j = 0; j < PL; ++j) {
+    if (!((bits >> j) & 1u)) continue;
+    const int h = h0 + j;
+    // value = lo + hi 2^48 + top 2^96, lo and hi in [0, 2^48): as a 128-bit integer
+    const unsigned long long l = sm.lo[h], x = (unsigned long long)sm.hi[h];
+    const long long t = sm.top[h];
+    const uint64_t qlo = l | (x << 48);
+    const uint64_t qhi = (x >> 16) | ((uint64_t)t << 32);
+    const V hv = from_fixed_as<V>(qlo, qhi, F);
+    const uint32_t k = kmin + (uint32_t)h;
+    tcol[pos] = (int32_t)(k & cmask);
+    tval[pos] = hv;
+    if constexpr (RES) tres[pos] = fixed_residual<V>(qlo, qhi, F, hv);
+    atomicAdd(&sm.rowcnt[k >> colbits], 1u);
+    sm.lo[h] = 0ull;
+    sm.hi[h] = 0ll;
+    sm.top[h] = 0ll;
+    ++pos;
+  }
+  __syncthreads();
+  if (threadIdx.x < kLeafKeys / 32) sm.occ[threadIdx.x] = 0u;
+  heavy_sync();
+  return total;
+}
+
+// split width for a key range of w keys: 0 for a leaf, else the digit shift
+__device__ __forceinline__ int heavy_shift(uint32_t w) {
+  if (w <= (uint32_t)kLeafKeys) return 0;
+  const int bits = 32 - __clz(w - 1);  // keys need `bits` bits
+  return bits - 10 > 12 ? bits - 10 : 12;
+}
+
+// (the pair buffers alias the output, so they carry no __restrict__)
+template <typename V, bool RES = false>
+__global__ __launch_bounds__(kHeavyThreads) void k_pass3_heavy(uint32_t* ikey, V* ival, uint32_t* akey, V* aval,
+                                                             const uint32_t* __restrict__ sbb, int s2, int colbits,
+                                                             int64_t n_node, const uint32_t* __restrict__ emax,
+                                                             V* __restrict__ tres, uint32_t* __restrict__ rowoff,
+                                                             uint32_t* __restrict__ usub,
+                                                             const uint32_t* __restrict__ ov_list,
+                                                             const uint32_t* __restrict__ ov_count) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const HeavySmem sm(smem);
+  const uint32_t n_over = *ov_count;
+  if (blockIdx.x >= n_over) return;
+  for (int h = threadIdx.x; h < kLeafKeys; h += kHeavyThreads) {
+    sm.lo[h] = 0ull;
+    sm.hi[h] = 0ll;
+    sm.top[h] = 0ll;
+  }
+  if (threadIdx.x < kLeafKeys / 32) sm.occ[threadIdx.x] = 0u;
+  const int F = 1117 - (int)*emax;
+  int32_t* const tcol = (int32_t*)akey;
+  for (uint32_t it = blockIdx.x; it < n_over; it += gridDim.x) {
+    const int64_t g = ov_list[it];
+    const uint32_t beg = sbb[g], end = sbb[g + 1];
+    const int64_t r0 = g << s2;
+    const int R = (int)min((int64_t)1 << s2, n_node - r0);
+    for (int r = threadIdx.x; r < 256; r += kHeavyThreads) sm.rowcnt[r] = 0u;
+    // key range
+    uint32_t mn = 0xFFFFFFFFu, mx = 0u;
+      heavy_stream<false>(ikey, ival, beg, end, [&](uint32_t k, V, bool ok) {
+      mn = ok && k < mn ? k : mn;
+      mx = ok && k > mx ? k : mx;
+    });
+    if (threadIdx.x < 2) sm.misc[threadIdx.x] = threadIdx.x == 0 ? 0xFFFFFFFFu : 0u;
+    __syncthreads();
+    atomicMin(&sm.misc[0], mn);
+    atomicMax(&sm.misc[1], mx);
+    __syncthreads();
+    const uint32_t kmin = sm.misc[0], w0 = sm.misc[1] - kmin + 1;
+    __syncthreads();
+    uint32_t U = 0;
+    const int sh0 = heavy_shift(w0);
+    if (sh0 == 0) {
+      U = heavy_leaf<V, RES>(sm, ikey, ival, beg, end, kmin, F, colbits, tcol + beg, aval + beg,
+                             RES ? tres + beg : nullptr, 0);
+    } else {
+      const int nd0 = (int)((w0 - 1) >> sh0) + 1;
+      uint32_t* st0 = sm.start;
+      heavy_split<V>(sm, ikey, ival, akey, aval, beg, end, kmin, sh0, nd0, st0);
+      for (int d0 = 0; d0 < nd0; ++d0) {
+        const uint32_t a = st0[d0], b = st0[d0 + 1];
+        if (a == b) continue;
+        const uint32_t k0 = kmin + ((uint32_t)d0 << sh0);
+        const uint32_t w1 = (1u << sh0) < (kmin + w0 - k0) ? (1u << sh0) : (kmin + w0 - k0);
+        const int sh1 = heavy_shift(w1);
+        if (sh1 == 0) {  // a leaf, in the alternate buffer
+          U += heavy_leaf<V, RES>(sm, akey, aval, a, b, k0, F, colbits, tcol + beg, aval + beg,
+                                  RES ? tres + beg : nullptr, U);
+          continue;
+        }
+        const int nd1 = (int)((w1 - 1) >> sh1) + 1;
+        uint32_t* st1 = sm.start + (kDigits + 1);
+        heavy_split<V>(sm, akey, aval, ikey, ival, a, b, k0, sh1, nd1, st1);
+        for (int d1 = 0; d1 < nd1; ++d1) {  // leaves (sh1 = 12 after a first split)
+          const uint32_t a1 = st1[d1], b1 = st1[d1 + 1];
+          if (a1 == b1) continue;
+          U += heavy_leaf<V, RES>(sm, ikey, ival, a1, b1, k0 + ((uint32_t)d1 << sh1), F, colbits, tcol + beg,
+                                  aval + beg, RES ? tres + beg : nullptr, U);
+        }
+      }
+    }
+    // row offsets within the sub-bucket
+    if (threadIdx.x < 64) {
+      const int lane = threadIdx.x;
+      uint32_t v[4], sum = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int r = lane * 4 + k;
+        v[k] = r < R ? sm.rowcnt[r] : 0u;
+        sum += v[k];
+      }
+      uint32_t x = sum;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+      }
+      uint32_t run = x - sum;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int r = lane * 4 + k;
+        if (r < R) rowoff[r0 + r] = run;
+        run += v[k];
+      }
+    }
+    if (threadIdx.x == 0) usub[g] = U;
+    heavy_sync();
+  }
 }
 
 // ------------------------------------------------------------------------- final

@@ -40,7 +40,8 @@ def test_header_constants_match_binding():
 def test_struct_layout():
     assert ctypes.sizeof(KbMesh) == 48
     assert KbMesh.conn.offset == 24 and KbMesh.coef.offset == 40
-    assert ctypes.sizeof(KbTuning) == 24 and KbTuning.stage_events.offset == 16
+    assert ctypes.sizeof(KbTuning) == 32 and KbTuning.stage_events.offset == 16
+    assert KbTuning.seg_pairs.offset == 24 and KbTuning.reserved.offset == 28
 
 
 def _plan(elem, nel, nn, prec=0, tuning=None):
@@ -54,7 +55,7 @@ def _plan(elem, nel, nn, prec=0, tuning=None):
 
 def test_version_and_strings():
     L = _lib.lib()
-    assert L.kb_version() == 2
+    assert L.kb_version() == 3
     assert L.kb_status_string(0) == b"ok"
     assert L.kb_status_string(-3) == b"workspace too small"
     assert L.kb_status_string(16) == b"nnz exceeds capacity"
@@ -108,6 +109,10 @@ def test_plan_errors():
     assert _plan(8, 10, 10, tuning=KbTuning(0, 3, 0.0, 5, None))[0] == _lib.KB_EINVAL  # sub > bucket
     assert _plan(8, 10, 10, tuning=KbTuning(0, 20, 0.0, 2, None))[0] == _lib.KB_EINVAL  # > 1024 sub-buckets
     assert _plan(8, 10, 10, tuning=KbTuning(512, 10, 8.0, 4, None))[0] == 0
+    assert _plan(8, 10, 10, tuning=KbTuning(0, 0, 0.0, 0, None, 2048, 0))[0] == _lib.KB_EINVAL  # segment length
+    assert _plan(8, 10, 10, tuning=KbTuning(0, 0, 0.0, 0, None, 0, 1))[0] == _lib.KB_EINVAL  # reserved
+    assert _plan(8, 10, 10, tuning=KbTuning(0, 0, 0.0, 0, None, 8192, 0))[0] == 0
+    assert _plan(4, 10, 10, tuning=KbTuning(0, 0, 0.0, 0, None, 4096, 0))[0] == 0
 
 
 def test_build_argument_errors_return_before_any_launch():
@@ -320,3 +325,16 @@ def test_grouped_argument_errors():
     assert call(g=0) == _lib.KB_EINVAL
     for k in ("ws", "rp", "col", "val", "nnz", "st"):
         assert call(**{k: None}) == _lib.KB_EINVAL, k
+
+
+@pytest.mark.parametrize("elem", [4, 8])
+@pytest.mark.parametrize("prec", [0, 2])
+def test_plan_widens_buckets_for_very_many_rows(elem, prec):
+    """With the default tuning, the plan widens the row buckets (and narrows the tile) so
+    that pass 1's bucket counters fit in LDS: up to 2^27 rows; 2^28 rows are refused (the
+    sub-bucket key has no room left for the row beside a 28-bit column)."""
+    for nn in (80_000_000, 2**27):
+        nel = min(nn * (6 if elem == 4 else 1), 2**31 // (10 if elem == 4 else 36) - 1)
+        rc, ws, nt = _plan(elem, nel, nn, prec)
+        assert rc == 0, nn
+    assert _plan(elem, 1000, 2**28, prec)[0] == _lib.KB_EINVAL

@@ -139,10 +139,11 @@ def test_adjoint_c5_full():
 
 
 def test_degenerate_element_is_flagged():
-    """Two tets sharing a face, the second flat (its fourth node in the shared face):
-    det = 0 there.  The adjoint flags it (inverted, non-finite) and leaves its node
-    contributions out; the first element's own gradients still match the oracle."""
-    X = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1], [1 / 3, 1 / 3, 1 / 3]], float)
+    """Two tets sharing a face, the second flat (its fourth node in the shared face,
+    at coordinates exact in binary so that det = 0 exactly).  The adjoint flags it
+    (inverted, non-finite) and leaves its node contributions out; the first element's
+    own gradients still match the oracle."""
+    X = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1], [0.25, 0.25, 0.5]], float)
     m = meshgen.Mesh(4, np.array([[0, 1, 2, 3], [1, 2, 3, 4]], np.int32), X, np.array([1.5, 0.5]))
     conn, coords, coef = to_dev(m)
     allow = kb._lib.KB_F_INVERTED | kb._lib.KB_F_NONFINITE

@@ -190,3 +190,30 @@ def test_batch_bad_node_offsets_stay_in_bounds(case):
     assert int(b.nnz_off.abs().sum().item()) == 0
     with pytest.raises(kb.KBuildError):
         b.results(check=True)
+
+
+def test_autotune_batch_valid_cached_and_bit_equal(tmp_path):
+    """The tuning search on a small batch: its choice is valid for the shape, is stored in
+    the JSON cache and read back from it, and builds the batch bit for bit as the
+    built-in choice does (every candidate runs the same kernels on the same inputs)."""
+    meshes = small_batch(8, 10, seed=21, hi=8)
+    batch = kb.pack_batch(as_tuples(meshes), 8, "cuda")
+    cache = str(tmp_path / "tuning.json")
+    t, entry = kb.tune_batch(batch, "fp32fb64", cache_path=cache)
+    say(f"[autotune] chose {t} in {entry['ms']:.3f} ms (built-in {entry['default_ms']:.3f} ms, "
+        f"{entry['candidates_timed']} candidates timed)")
+    assert entry["source"] == "search" and entry["candidates_timed"] >= 4
+    assert entry["ms"] <= entry["default_ms"]
+    kb.plan_batched(8, batch.n_mesh, batch.conn.shape[0], batch.coords.shape[0], "fp32fb64", t)  # valid
+    tuned = kb.BatchBuilder(batch, "fp32fb64", "auto", tune_cache=cache)
+    assert tuned.tune_entry["source"] == "cache" and tuned.tuning == t
+    base = kb.BatchBuilder(batch, "fp32fb64")
+    tuned.run()
+    base.run()
+    rt, rb = tuned.results(), base.results()
+    assert torch.equal(tuned.nnz_off, base.nnz_off)
+    for a, b in zip(rt, rb):
+        assert torch.equal(a.row_ptr, b.row_ptr) and torch.equal(a.col_idx, b.col_idx)
+        assert torch.equal(a.vals.view(torch.int32), b.vals.view(torch.int32))
+    err = check_against_oracle(meshes, rt, "fp32fb64")
+    assert err <= TOL["fp32fb64"]

@@ -8,7 +8,9 @@ into the next group's pass) on the GPU, through the C ABI:
   capacity rule; an empty mesh;
 * a Kuhn tet box of 6 x 337^3 = 229,636,518 elements, whose 2,296,365,180 element
   pairs exceed what one pass indexes (2^31), built in two groups: nnz against the
-  closed form, sampled rows against the oracle, zero row sums of the whole matrix.
+  closed form, sampled rows against the oracle, zero row sums of the whole matrix;
+* the groups streamed from pinned host memory (kb_build_lower_csr_group_pass), equal to
+  the device-resident grouped build bit for bit.
 """
 from __future__ import annotations
 
@@ -140,3 +142,34 @@ def test_grouped_heavy_row_takes_the_fallback_path():
     m = _fan(20000, center_last=True, seed=3)
     compare_to_single(m, "fp64", 6000)
     compare_to_single(m, "fp32fb64", 6000)
+
+
+@pytest.mark.parametrize("prec", ["fp32fb64", "fp64"])
+def test_streamed_groups_from_host_memory(prec):
+    """Connectivity and coefficients in pinned host memory, streamed group by group into
+    two device staging buffers while the previous group's pass runs: the result is the
+    device-resident grouped build's bit for bit (the same passes in the same order), on
+    two runs in a row, and agrees with the oracle."""
+    m = meshgen.config_mesh(3, n=40)
+    group = m.n_elem // 4 + 17  # four groups, the last one short
+    say(f"[streamed] {prec} nel={m.n_elem} group={group}")
+    dev = to_dev(m)
+    one = kb.build_lower_csr(*dev, 4, prec=prec)
+    ref = kb.build_lower_csr_grouped(*dev, 4, group, cap=one.nnz, prec=prec)
+    conn_h = torch.from_numpy(m.conn).pin_memory()
+    coef_h = torch.from_numpy(m.coef).pin_memory()
+    sb = kb.StreamedGroupedBuilder(4, m.n_elem, m.n_node, group, one.nnz, prec=prec)
+    assert sb.n_groups == 4
+    for _ in range(2):
+        sb.run(conn_h, dev[1], coef_h)
+        r = sb.result()
+        assert r.nnz == ref.nnz
+        assert torch.equal(r.row_ptr, ref.row_ptr) and torch.equal(r.col_idx, ref.col_idx)
+        assert torch.equal(r.vals, ref.vals)
+    orp, ocol, oval, _ = oracle.build_mesh(m)
+    rp, col, val = (t.cpu().numpy() for t in (r.row_ptr, r.col_idx, r.vals))
+    np.testing.assert_array_equal(rp, orp)
+    np.testing.assert_array_equal(col, ocol)
+    assert scaled_error(orp, ocol, val.astype(np.float64), oval) <= TOL[prec]
+    with pytest.raises(ValueError):  # device tensors are refused: the path reads host memory
+        sb.run(dev[0], dev[1], dev[2])

@@ -7,6 +7,8 @@ the launch still spans many workgroups and ends in a ragged tail.
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -204,20 +206,29 @@ def test_unused_nodes_have_empty_rows():
 
 
 def _fan(n_tets, center_last, seed=0):
-    """n_tets tets sharing one node: its row (or diagonal) collects every element."""
+    """n_tets tets sharing one node: its row (or diagonal) collects every element.  Each
+    tet is the corner tet (0, e1, e2, e3), jittered by 0.2, scaled by 0.5..2 and turned
+    by a random rotation: shapes stay well conditioned, so FP64 integration error stays
+    near rounding (randomly placed corners make nearly flat tets whose values carry
+    relative errors of 1e-11 in any FP64 evaluation)."""
     rng = np.random.default_rng(seed)
     nn = 1 + 3 * n_tets
-    X = rng.standard_normal((nn, 3))
-    X[0] = 0.0
-    conn = np.zeros((n_tets, 4), np.int32)
-    for t in range(n_tets):
-        conn[t] = [0, 1 + 3 * t, 2 + 3 * t, 3 + 3 * t]
-        M = np.hstack([np.ones((4, 1)), X[conn[t]]])
-        if np.linalg.det(M) < 0:
-            conn[t, [2, 3]] = conn[t, [3, 2]]
+    Q, Rq = np.linalg.qr(rng.standard_normal((n_tets, 3, 3)))
+    Q = Q * np.sign(np.diagonal(Rq, axis1=1, axis2=2))[:, None, :]
+    Q[np.linalg.det(Q) < 0, :, 0] *= -1.0  # proper rotations
+    corner = np.eye(3)[None] + 0.2 * rng.standard_normal((n_tets, 3, 3))  # rows: the three corners
+    scale = rng.uniform(0.5, 2.0, (n_tets, 1, 1))
+    X = np.zeros((nn, 3))
+    X[1:] = (scale * corner @ np.transpose(Q, (0, 2, 1))).reshape(-1, 3)
+    t = np.arange(n_tets)
+    conn = np.stack([np.zeros(n_tets, np.int64), 1 + 3 * t, 2 + 3 * t, 3 + 3 * t], axis=1)
+    # orientation: det [1 x_a]_(a=0..3) with x_0 = 0 is det [x_1; x_2; x_3]
+    neg = np.linalg.det(X[conn[:, 1:]]) < 0
+    conn[neg, 2], conn[neg, 3] = conn[neg, 3].copy(), conn[neg, 2].copy()
+    conn = conn.astype(np.int32)
     if center_last:
         # relabel: centre gets the largest id, so its row holds 4 entries per element
-        perm = np.roll(np.arange(nn), -1)  # old 0 -> nn-1, old i -> i-1
+        perm = np.roll(np.arange(nn), 1)  # old 0 -> nn-1, old i -> i-1
         newX = np.empty_like(X)
         newX[perm] = X
         conn = perm[conn].astype(np.int32)
@@ -225,19 +236,34 @@ def _fan(n_tets, center_last, seed=0):
     return meshgen.Mesh(4, conn, X, np.exp(rng.uniform(-2, 2, n_tets)))
 
 
-@pytest.mark.parametrize("n_tets,center_last", [(5000, False), (5000, True), (20000, True)])
+@pytest.mark.parametrize("n_tets,center_last", [(5000, False), (5000, True), (20000, True), (200000, True),
+                                                (1_500_000, True)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32fb64"])
 def test_heavy_row(n_tets, center_last, prec):
-    """A node shared by thousands of elements.  With the centre last, its row holds
-    3 n + 1 distinct entries (more than any LDS hash table: global path); with 20000 tets
-    its sub-bucket also exceeds 2^16 pairs (the chunk-sum bound: global path)."""
+    """A node shared by n elements.  With the centre last, its row holds 3 n + 1 distinct
+    entries (more than any LDS hash table: the heavy-sub-bucket kernel); from 20000 tets
+    its sub-bucket also exceeds 2^16 pairs and its diagonal sums n pairs over several
+    carry rounds; 200000 tets split the row once into leaf ranges, 1.5M tets (4.5M
+    columns, more than 2^22) split it twice."""
     m = _fan(n_tets, center_last)
+    say(f"[heavy] n={n_tets} centre_last={center_last} {prec}")
     r = gpu_build(m, prec)
     rp, col, val = np_csr(r)
     orp, ocol, oval, _ = oracle.build_mesh(m)
     np.testing.assert_array_equal(rp, orp)
     np.testing.assert_array_equal(col, ocol)
-    assert scaled_error(orp, ocol, val, oval) <= TOL[prec]
+    # the centre's diagonal sums one value per element.  The oracle sums in sequence, so
+    # its own rounding error grows to about n * 2^-53 of the sum (2e-11 at 200000 terms,
+    # above the FP64 tolerance); that entry is referenced to the correctly rounded sum of
+    # the oracle's element values instead (each element's (0, 0) value: the centre is
+    # its first node)
+    c = m.n_node - 1 if center_last else 0
+    klow, _ = oracle.integrate_lower(m.elem, m.conn, m.coords, m.coef)
+    oval = oval.copy()
+    oval[orp[c + 1] - 1] = math.fsum(klow[:, 0].tolist())
+    err = scaled_error(orp, ocol, val, oval)
+    say(f"  nnz={len(col):,} scaled error {err:.2e}")
+    assert err <= TOL[prec]
 
 
 def test_capacity_flag():
@@ -294,3 +320,22 @@ def test_fallback_fires_on_distorted_mesh():
     say(f"  fallback elements {r.n_fallback} of {m.n_elem}")
     assert r.n_fallback > 0
     assert scaled_error(orp, ocol, val, oval) <= TOL["fp32fb64"]
+
+
+def test_lower_csr_tensor():
+    """The build as torch.sparse_csr_tensor: the same row pointers, columns and values as
+    the CSR arrays, int32 indices, usable by torch's sparse products (K x against the
+    oracle's matrix)."""
+    m = MESHES["c3_tet9"]
+    t = kb.lower_csr_tensor(*to_dev(m), m.elem, prec="fp64")
+    assert t.layout == torch.sparse_csr and t.shape == (m.n_node, m.n_node)
+    assert t.crow_indices().dtype == torch.int32 and t.col_indices().dtype == torch.int32
+    orp, ocol, oval, _ = oracle.build_mesh(m)
+    np.testing.assert_array_equal(t.crow_indices().cpu().numpy(), orp)
+    np.testing.assert_array_equal(t.col_indices().cpu().numpy(), ocol)
+    x = np.random.default_rng(1).standard_normal(m.n_node)
+    y = (t.to(torch.float64) @ torch.from_numpy(x).cuda()).cpu().numpy()
+    rows = np.repeat(np.arange(m.n_node), np.diff(orp))
+    ref = np.zeros(m.n_node)
+    np.add.at(ref, rows, oval * x[ocol])
+    assert np.max(np.abs(y - ref)) <= 1e-12 * np.max(np.abs(ref))
