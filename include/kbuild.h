@@ -41,7 +41,8 @@
  * and kb_tuning structs themselves, which are host memory read during the call).
  * The caller owns and allocates all memory; the library allocates nothing and keeps
  * no state between calls apart from a per-device cache of the compute-unit count
- * (read once with hipDeviceGetAttribute).  Work is enqueued on `stream` (a hipStream_t)
+ * (read once with hipDeviceGetAttribute) and, for kb_build_lower_csr_noalloc only, a
+ * fixed per-device scratch array and its device address.  Work is enqueued on `stream` (a hipStream_t)
  * and the calls return without synchronising; results are valid once the stream
  * reaches that point.  Calls that share a workspace must be ordered on one stream.
  * The output of a call is bitwise deterministic for given inputs and precision.
@@ -167,6 +168,27 @@ int kb_plan(const kb_mesh* mesh, int prec, const kb_tuning* tuning, size_t* ws_b
 int kb_build_lower_csr(const kb_mesh* mesh, int prec, const kb_tuning* tuning, void* ws, size_t ws_bytes,
                        int32_t* row_ptr, int32_t* col_idx, void* vals, int64_t cap, int64_t* nnz_dev,
                        uint32_t* status_dev, void* stream);
+
+/*
+ * kb_build_lower_csr without a caller workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  The workspace is a fixed array of KB_SCRATCH_BYTES inside the
+ * library: one copy per device, held from the library's first use on that device until
+ * the process ends.  The call allocates nothing (no hipMalloc, no allocating library
+ * routine); its first call on a device looks up that device's copy of the array.
+ *   Arguments, outputs and errors as for kb_build_lower_csr (without ws / ws_bytes);
+ *   KB_ENOSPC when kb_plan's workspace figure for this mesh exceeds KB_SCRATCH_BYTES
+ *   (about 3e6 lower pairs in FP32: e.g. 300,000 tetrahedra or 80,000 bricks), KB_EHIP
+ *   when the array's device address cannot be found.
+ * Every call on one device uses that device's single array: calls that overlap on one
+ * device (other streams, other host threads) race and corrupt each other's results, so
+ * the caller orders them (one stream, or events).  The array keeps the last call's
+ * contents; the build initialises every part of it that it reads.
+ */
+#define KB_SCRATCH_BYTES (64u << 20)
+int kb_build_lower_csr_noalloc(const kb_mesh* mesh, int prec, const kb_tuning* tuning, int32_t* row_ptr,
+                               int32_t* col_idx, void* vals, int64_t cap, int64_t* nnz_dev, uint32_t* status_dev,
+                               void* stream);
 
 /*
  * Integration only (Alg. 2): vals device [n_elem][nen*(nen+1)/2] of double (KB_FP64)

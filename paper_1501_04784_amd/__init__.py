@@ -236,6 +236,22 @@ def lower_csr_tensor(conn, coords, coef, elem: int, prec="fp32fb64", tuning: Tun
     return build_lower_csr(conn, coords, coef, elem, prec=prec, tuning=tuning, op=op).to_torch()
 
 
+def build_lower_csr_noalloc(conn, coords, coef, elem: int, row_ptr, col_idx, vals, nnz_dev, status, prec="fp32fb64",
+                            tuning: Tuning | None = None, op="stiffness", stream=None):
+    """Enqueue a full construction into caller-allocated outputs through
+    ``kb_build_lower_csr_noalloc``: the library's fixed per-device scratch replaces the
+    workspace, and nothing is allocated (outputs as for ``Builder``; the mesh's workspace
+    must fit ``KB_SCRATCH_BYTES``).  Calls on one device must not overlap."""
+    _validate_mesh(conn, coords, coef, elem)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    tu = (tuning or Tuning()).to_c()
+    m = _mesh(elem, conn.shape[0], coords.shape[0], conn, coords, coef, op)
+    rc = _lib.lib().kb_build_lower_csr_noalloc(ctypes.byref(m), _prec(prec), ctypes.byref(tu), _ptr(row_ptr),
+                                               _ptr(col_idx), _ptr(vals), int(col_idx.numel()), _ptr(nnz_dev),
+                                               _ptr(status), ctypes.c_void_p(s.cuda_stream))
+    _check(rc, "kb_build_lower_csr_noalloc")
+
+
 def assemble_lower_csr(conn, n_node: int, klow, elem: int, prec="fp64", tuning: Tuning | None = None, check=True,
                        allow_flags: int = 0, cap: int | None = None, dof: int = 1) -> LowerCSR:
     """Assemble lower CSR K from given per-element lower values klow [n_elem, nd(nd+1)/2],
@@ -617,7 +633,7 @@ def build_lower_csr_batched(meshes, elem: int, prec="fp32fb64", tuning: Tuning |
 
 
 __all__ = ["Builder", "BatchBuilder", "Batch", "GroupedBuilder", "StreamedGroupedBuilder", "LowerCSR", "KBuildError", "Tuning", "build_lower_csr",
-           "lower_csr_tensor",
+           "build_lower_csr_noalloc", "lower_csr_tensor",
            "build_lower_csr_batched", "assemble_lower_csr", "integrate_lower", "adjoint_lower", "AdjointBuilder",
            "lower_csr_values",
            "pack_batch", "plan", "plan_batched",

@@ -14,10 +14,11 @@ KB_OK, KB_EINVAL, KB_ERANGE, KB_ENOSPC, KB_EHIP = 0, -1, -2, -3, -4
 KB_STATUS_WORDS = 4
 KB_F_INDEX, KB_F_REPEAT, KB_F_INVERTED, KB_F_NONFINITE, KB_F_CAPACITY = 1, 2, 4, 8, 16
 KB_N_STAGES = 8
+KB_SCRATCH_BYTES = 64 << 20  # fixed workspace of kb_build_lower_csr_noalloc
 STAGE_NAMES = ("init", "count", "offsets", "integrate", "histogram", "partition", "reduce", "compress")
 
 # every function declared in include/kbuild.h
-EXPORTS = ("kb_plan", "kb_build_lower_csr", "kb_integrate_lower", "kb_assemble_lower_csr", "kb_plan_dof",
+EXPORTS = ("kb_plan", "kb_build_lower_csr", "kb_build_lower_csr_noalloc", "kb_integrate_lower", "kb_assemble_lower_csr", "kb_plan_dof",
            "kb_assemble_lower_csr_dof", "kb_plan_grouped", "kb_build_lower_csr_grouped",
            "kb_build_lower_csr_group_pass", "kb_plan_batched", "kb_build_lower_csr_batched", "kb_plan_adjoint",
            "kb_adjoint_lower", "kb_status_string", "kb_version")
@@ -79,6 +80,8 @@ def lib():
         L.kb_plan.restype = i32
         L.kb_build_lower_csr.argtypes = [PM, i32, PT, p, sz, p, p, p, i64, p, p, p]
         L.kb_build_lower_csr.restype = i32
+        L.kb_build_lower_csr_noalloc.argtypes = [PM, i32, PT, p, p, p, i64, p, p, p]
+        L.kb_build_lower_csr_noalloc.restype = i32
         L.kb_integrate_lower.argtypes = [PM, i32, PT, p, p, p]
         L.kb_integrate_lower.restype = i32
         L.kb_assemble_lower_csr.argtypes = [PM, i32, PT, p, p, sz, p, p, p, i64, p, p, p]

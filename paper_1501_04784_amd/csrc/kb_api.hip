@@ -719,6 +719,27 @@ int check_mesh_ptrs(const kb_mesh* m, bool need_geometry) {
 
 }  // namespace
 
+// Fixed scratch of kb_build_lower_csr_noalloc: one copy per device, resident until the
+// process ends.  Host code never uses the array's name as an address: the device address
+// is looked up once per device (hipGetSymbolAddress) and kept in scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[KB_SCRATCH_BYTES];
+
+static constexpr int kMaxDevices = 64;
+
+// device address of this device's scratch array, looked up on the first call per device
+static int scratch_address(void** out) {
+  static std::atomic<void*> scratch_ptr[kMaxDevices];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return KB_EHIP;
+  void* ptr = scratch_ptr[dev].load(std::memory_order_acquire);
+  if (!ptr) {
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return KB_EHIP;
+    scratch_ptr[dev].store(ptr, std::memory_order_release);
+  }
+  *out = ptr;
+  return KB_OK;
+}
+
 extern "C" {
 
 int kb_version(void) { return KB_VERSION; }
@@ -747,14 +768,21 @@ int kb_plan(const kb_mesh* mesh, int prec, const kb_tuning* tuning, size_t* ws_b
   return KB_OK;
 }
 
+// use_scratch: the library's fixed scratch array is the workspace (ws, ws_bytes ignored);
+// every host check comes before the device is touched
 static int build_common(const kb_mesh* mesh, int prec, const kb_tuning* tuning, const void* klow, void* ws,
                         size_t ws_bytes, int32_t* row_ptr, int32_t* col_idx, void* vals, int64_t cap, int64_t* nnz_dev,
-                        uint32_t* status_dev, void* stream) {
+                        uint32_t* status_dev, void* stream, bool use_scratch = false) {
   Plan p;
   KB_TRY(make_plan(mesh, prec, tuning, &p));
   KB_TRY(check_mesh_ptrs(mesh, klow == nullptr));
   if (!row_ptr || !nnz_dev || !status_dev || cap < 0) return KB_EINVAL;
   if (cap > 0 && (!col_idx || !vals)) return KB_EINVAL;
+  if (use_scratch) {
+    if (p.total > (size_t)KB_SCRATCH_BYTES) return KB_ENOSPC;
+    KB_TRY(scratch_address(&ws));
+    ws_bytes = (size_t)KB_SCRATCH_BYTES;
+  }
   if (ws_bytes < p.total) return KB_ENOSPC;
   if (p.total > 0 && !ws) return KB_EINVAL;
   KB_TRY(device_cus(&p.cus));
@@ -770,6 +798,13 @@ int kb_build_lower_csr(const kb_mesh* mesh, int prec, const kb_tuning* tuning, v
                        uint32_t* status_dev, void* stream) {
   return build_common(mesh, prec, tuning, nullptr, ws, ws_bytes, row_ptr, col_idx, vals, cap, nnz_dev, status_dev,
                       stream);
+}
+
+int kb_build_lower_csr_noalloc(const kb_mesh* mesh, int prec, const kb_tuning* tuning, int32_t* row_ptr,
+                               int32_t* col_idx, void* vals, int64_t cap, int64_t* nnz_dev, uint32_t* status_dev,
+                               void* stream) {
+  return build_common(mesh, prec, tuning, nullptr, nullptr, 0, row_ptr, col_idx, vals, cap, nnz_dev, status_dev,
+                      stream, true);
 }
 
 int kb_assemble_lower_csr(const kb_mesh* mesh, int prec, const kb_tuning* tuning, const void* klow, void* ws,

@@ -327,6 +327,32 @@ def test_grouped_argument_errors():
         assert call(**{k: None}) == _lib.KB_EINVAL, k
 
 
+def test_noalloc_host_errors_before_any_device_call():
+    """kb_build_lower_csr_noalloc checks its arguments and the mesh's workspace figure
+    against the fixed scratch size on the host, before it looks up the scratch array."""
+    L = _lib.lib()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced
+    src = open(HEADER).read()
+    scratch = int(eval(re.search(r"#define\s+KB_SCRATCH_BYTES\s+\((\d+)u\s*<<\s*(\d+)\)", src).expand(r"\1 << \2")))
+    assert scratch == _lib.KB_SCRATCH_BYTES
+
+    def call(m, prec=1, row_ptr=fake, cap=10):
+        return L.kb_build_lower_csr_noalloc(ctypes.byref(m), prec, None, row_ptr, fake, fake, cap, fake, fake, None)
+
+    # the largest tet mesh whose workspace fits, and one beyond (plan figures only)
+    ok = KbMesh(4, 0, 200_000, 40_000, 0x1000, 0x1000, 0x1000)
+    assert _plan(4, 200_000, 40_000, 1)[1] <= scratch
+    big = KbMesh(4, 0, 2_000_000, 400_000, 0x1000, 0x1000, 0x1000)
+    assert _plan(4, 2_000_000, 400_000, 1)[1] > scratch
+    assert call(big) == _lib.KB_ENOSPC
+    assert call(KbMesh(5, 0, 10, 10, 0x1000, 0x1000, 0x1000)) == _lib.KB_EINVAL
+    assert call(ok, prec=7) == _lib.KB_EINVAL
+    assert call(ok, row_ptr=None) == _lib.KB_EINVAL
+    assert call(ok, cap=-1) == _lib.KB_EINVAL
+    ok.coords = None
+    assert call(ok) == _lib.KB_EINVAL
+
+
 @pytest.mark.parametrize("elem", [4, 8])
 @pytest.mark.parametrize("prec", [0, 2])
 def test_plan_widens_buckets_for_very_many_rows(elem, prec):

@@ -1,0 +1,78 @@
+"""The allocation-free build (kb_build_lower_csr_noalloc, fixed per-device scratch) against
+kb_build_lower_csr with a caller workspace: two calls in a row through the C ABI, the
+second on a smaller mesh, every output bit for bit equal to the workspace build's, and
+the pattern and values checked against the FP64 oracle.  Oversized meshes are refused."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import meshgen
+import oracle
+import paper_1501_04784_amd as kb
+from paper_1501_04784_amd import _lib
+from tests.gpu_common import TOL, np_csr, say, to_dev
+from tests.helpers import scaled_error
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # collected on CPU only when -m gpu is asked for explicitly
+    pytest.skip("no GPU", allow_module_level=True)
+
+
+def _outputs(m, prec):
+    d = torch.device("cuda:0")
+    T = m.n_elem * m.elem * (m.elem + 1) // 2
+    return (torch.full((m.n_node + 1,), -7, dtype=torch.int32, device=d),
+            torch.full((max(T, 1),), -7, dtype=torch.int32, device=d),
+            torch.full((max(T, 1),), float("nan"), dtype=kb.value_dtype(prec), device=d),
+            torch.zeros(1, dtype=torch.int64, device=d), torch.zeros(_lib.KB_STATUS_WORDS, dtype=torch.int32, device=d))
+
+
+def _noalloc(m, prec):
+    conn, coords, coef = to_dev(m)
+    rp, col, val, nnz, st = _outputs(m, prec)
+    kb.build_lower_csr_noalloc(conn, coords, coef, m.elem, rp, col, val, nnz, st, prec=prec)
+    torch.cuda.synchronize()
+    n = int(nnz.item())
+    assert int(st[0].item()) == 0, int(st[0].item())
+    return rp.cpu().numpy(), col[:n].cpu().numpy(), val[:n].cpu().numpy(), int(st[1].item())
+
+
+@pytest.mark.parametrize("prec", ["fp32fb64", "fp64"])
+@pytest.mark.parametrize("elem", [4, 8])
+def test_noalloc_matches_workspace_build_twice(elem, prec):
+    cid = 3 if elem == 4 else 2
+    sizes = (30, 9) if elem == 4 else (40, 7)  # the second call is smaller than the first
+    for n in sizes:
+        m = meshgen.config_mesh(cid, n=n)
+        ws_bytes, _ = kb.plan(m.elem, m.n_elem, m.n_node, prec)
+        assert ws_bytes <= _lib.KB_SCRATCH_BYTES
+        say(f"[noalloc] elem={elem} {prec} n={n} nel={m.n_elem:,} workspace {ws_bytes / 2**20:.1f} MiB")
+        rp, col, val, nfb = _noalloc(m, prec)
+        ref = kb.build_lower_csr(*to_dev(m), m.elem, prec=prec)
+        rrp, rcol, rval = (t.cpu().numpy() for t in (ref.row_ptr, ref.col_idx, ref.vals))
+        np.testing.assert_array_equal(rp, rrp)
+        np.testing.assert_array_equal(col, rcol)
+        assert val.dtype == rval.dtype and np.array_equal(val.view(np.uint8), rval.view(np.uint8))
+        assert nfb == ref.n_fallback
+        orp, ocol, oval, flags = oracle.build_mesh(m)
+        assert flags == 0
+        np.testing.assert_array_equal(rp, orp)
+        np.testing.assert_array_equal(col, ocol)
+        err = scaled_error(orp, ocol, val.astype(np.float64), oval)
+        say(f"  nnz={len(col):,} bit-equal to the workspace build; scaled error vs oracle {err:.2e}")
+        assert err <= TOL[prec]
+
+
+def test_noalloc_refuses_a_mesh_beyond_the_scratch():
+    m = meshgen.config_mesh(3, n=60)  # 1.3M tets: its workspace is larger than the scratch
+    ws_bytes, _ = kb.plan(m.elem, m.n_elem, m.n_node, "fp32fb64")
+    assert ws_bytes > _lib.KB_SCRATCH_BYTES
+    conn, coords, coef = to_dev(m)
+    rp, col, val, nnz, st = _outputs(m, "fp32fb64")
+    with pytest.raises(kb.KBuildError, match="workspace too small"):
+        kb.build_lower_csr_noalloc(conn, coords, coef, m.elem, rp, col, val, nnz, st)
+    torch.cuda.synchronize()
+    assert int(rp[0].item()) == -7  # nothing was enqueued
