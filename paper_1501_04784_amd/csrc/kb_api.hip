@@ -32,6 +32,7 @@ constexpr int kTargetBuckets = 256;  // first-level buckets (pass-1 run length)
 constexpr double kSubEntries = 300;   // target distinct entries per sub-bucket
 constexpr int kHTMin = 512, kHTMax = 4096;
 constexpr int kHeavyGrid = 64;  // workgroups of k_pass3_heavy (each takes whole sub-buckets)
+constexpr unsigned kFinalHeavyGrid = 256;  // workgroups copying the entries of heavy sub-buckets
 constexpr double kHalfTileRatio = 16;   // pairs per tile x bucket histogram entry
 constexpr size_t kWideStage = 112640;  // staged pair bytes per pass-1 tile, elements of > 8 rows
 
@@ -491,12 +492,22 @@ int assemble_tail(const Plan& p, unsigned char* ws, int32_t* row_ptr, int32_t* c
   KB_TRY(scan((const int32_t*)usub, p.nsub, part, (int32_t*)ubase, nnz_dev, s));
   if (p.nsub > 0) {
     const unsigned gf = (unsigned)div_up(p.nsub, 4);
-    if (cr)
+    auto* ov_list = (const uint32_t*)(ws + p.o_ovl);
+    const uint32_t* ov_count = emax + 1;
+    if (cr) {
       k_final<V, true><<<gf, 256, 0, s>>>(sbb, ubase, tcol, tval, tres, rowoff, p.s2, p.nn, p.nsub, row_ptr, col_idx,
                                           vals, (V*)cr->res_out, cr->rows_out, cap, status);
-    else
+      KB_LAUNCH_CHECK();
+      k_final_heavy<V, true><<<kFinalHeavyGrid, 256, 0, s>>>(sbb, ubase, tcol, tval, tres, rowoff, p.s2, p.nn, p.nsub,
+                                                            ov_list, ov_count, col_idx, vals, (V*)cr->res_out,
+                                                            cr->rows_out, cap);
+    } else {
       k_final<V><<<gf, 256, 0, s>>>(sbb, ubase, tcol, tval, nullptr, rowoff, p.s2, p.nn, p.nsub, row_ptr, col_idx,
                                     vals, nullptr, nullptr, cap, status);
+      KB_LAUNCH_CHECK();
+      k_final_heavy<V><<<kFinalHeavyGrid, 256, 0, s>>>(sbb, ubase, tcol, tval, nullptr, rowoff, p.s2, p.nn, p.nsub,
+                                                      ov_list, ov_count, col_idx, vals, nullptr, nullptr, cap);
+    }
     KB_LAUNCH_CHECK();
   } else {
     k_scan_empty<<<1, 1, 0, s>>>(row_ptr, nullptr);

@@ -135,41 +135,27 @@ __device__ __forceinline__ void split48(uint64_t lo, uint64_t hi, uint64_t& c0, 
   c1 = (int64_t)((lo >> 48) | (hi << 16));
 }
 
-// The two chunks of split48 computed directly from |q| = m * 2^sh (m < 2^53) and the
-// sign, without forming the 128-bit integer: c0 = q mod 2^48, c1 = floor(q / 2^48).
-// Same truncation toward zero as to_fixed; no branches.
-__device__ __forceinline__ void chunks_from_mag(uint64_t m, int sh, bool neg, uint64_t& c0, int64_t& c1) {
-  constexpr uint64_t M48 = (1ull << 48) - 1;
-  // both shift directions are formed and one is selected (64-bit shifts use the
-  // amount mod 64, so out-of-range amounts are masked to zero explicitly)
-  const uint64_t ml = m << (sh & 63), mr = m >> (-sh & 63);
-  const uint64_t mag = sh >= 0 ? (sh < 64 ? ml : 0ull) : (sh > -64 ? mr : 0ull);
-  const uint64_t lo = mag & M48;  // low 48 bits of the (truncated) magnitude
-  const int hs = 48 - sh;         // m >> hs is the magnitude above bit 48
-  const uint64_t hl = m << (-hs & 63), hr = m >> (hs & 63);
-  const uint64_t hi = hs <= 0 ? hl : (hs < 64 ? hr : 0ull);
-  const uint64_t borrow = lo ? 1ull : 0ull;
-  c0 = neg ? ((1ull << 48) - lo) & M48 : lo;
-  c1 = neg ? -(int64_t)(hi + borrow) : (int64_t)hi;
-}
-
-// split48 chunks of trunc(v * 2^F) for a double or float value (non-finite: zero)
+// split48 chunks of trunc(v * 2^F) for a double or float value (non-finite: zero),
+// formed in FP64 arithmetic, where every step is exact: v 2^F only moves the exponent
+// (|q| < 2^95; a result below 2^-1022 truncates to 0 either way), trunc and floor give
+// integers, and c1 = floor(q / 2^48), c0 = q - c1 2^48 in [0, 2^48) are multiples of
+// q's last bit below 2^53 of it.  Each is then converted through two 32-bit halves.
+// The same integers as split48 of to_fixed's q, without forming the 128-bit integer and
+// without branches.
 __device__ __forceinline__ void to_chunks(double v, int F, uint64_t& c0, int64_t& c1) {
-  const uint64_t b = (uint64_t)__double_as_longlong(v);
-  const int E = (int)((b >> 52) & 0x7FF);
-  uint64_t m = b & ((1ull << 52) - 1);
-  m |= (E != 0) ? (1ull << 52) : 0ull;
-  m = (E == 0x7FF) ? 0ull : m;
-  chunks_from_mag(m, (E != 0 ? E : 1) - 1075 + F, (b >> 63) != 0, c0, c1);
+  const double d = isfinite(v) ? v : 0.0;
+  const double q = trunc(ldexp(d, F));
+  const double h = floor(ldexp(q, -48));
+  const double l = fma(h, -0x1p48, q);     // [0, 2^48)
+  const double lh = floor(ldexp(l, -32));  // [0, 2^16)
+  const double ll = fma(lh, -0x1p32, l);   // [0, 2^32)
+  c0 = ((uint64_t)(uint32_t)lh << 32) | (uint64_t)(uint32_t)ll;
+  const double hh = floor(ldexp(h, -32));  // |hh| < 2^15
+  const double hl = fma(hh, -0x1p32, h);   // [0, 2^32)
+  c1 = (int64_t)(((uint64_t)(int64_t)(int32_t)hh << 32) | (uint64_t)(uint32_t)hl);
 }
 __device__ __forceinline__ void to_chunks(float v, int F, uint64_t& c0, int64_t& c1) {
-  const uint32_t b = __float_as_uint(v);
-  const int E = (int)((b >> 23) & 0xFF);
-  uint32_t m = b & 0x7FFFFFu;
-  m |= (E != 0) ? 0x800000u : 0u;
-  m = (E == 0xFF) ? 0u : m;
-  // a float is m * 2^(E-150), the same value as its exact double
-  chunks_from_mag((uint64_t)m, (E != 0 ? E : 1) - 150 + F, (b >> 31) != 0, c0, c1);
+  to_chunks((double)v, F, c0, c1);  // a float is exactly a double
 }
 
 // chunk sums back to the exact 128-bit value
@@ -1210,7 +1196,7 @@ __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* _
 // more distinct entries than an LDS table, or more than 2^16 pairs) is reduced by one
 // 1024-lane workgroup, which splits it by key into ranges of at most kLeafKeys keys:
 //   - the key range [kmin, kmax] of the sub-bucket; a range wider than kLeafKeys is split
-//     into at most 1024 digit ranges of 2^shift keys (a histogram, its scan and a
+//     into at most 2048 digit ranges of 2^shift keys (a histogram, its scan and a
 //     scatter into the other buffer, at the same place), twice at most for 31-bit keys;
 //   - each leaf range (in key order) sums its pairs into a direct-addressed LDS table,
 //     one slot per key, with the exact chunk sums of pass 3, carried into a third word
@@ -1219,13 +1205,13 @@ __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* _
 // Output as pass 3.  The pairs alternate between (ikey, ival) and (akey, aval), the
 // pass-1 arrays, which also receive the output (tcol / tval): a leaf writes at most as
 // many entries as it has pairs, so the output never reaches a pair not yet read.
-constexpr int kLeafKeys = 4096, kHeavyThreads = 1024, kDigits = 1024;
+constexpr int kLeafKeys = 4096, kHeavyThreads = 1024, kDigits = 2048;
 
 struct HeavySmem {
   unsigned long long* lo;  // [kLeafKeys] sum of low 48-bit chunks
   long long* hi;           // [kLeafKeys] sum of signed high chunks (bits 48..)
   long long* top;          // [kLeafKeys] carries above bit 96
-  uint32_t* occ;           // [kLeafKeys / 32] occupied slots
+  uint8_t* occ;            // [kLeafKeys] 1 for an occupied slot (byte stores: no atomics)
   uint32_t* hist;          // [kDigits] digit counts, then cursors
   uint32_t* start;         // [2][kDigits + 1] digit starts of the two split levels
   uint32_t* rowcnt;        // [256] entries per row of the sub-bucket
@@ -1235,16 +1221,15 @@ struct HeavySmem {
     lo = (unsigned long long*)p;
     hi = (long long*)(lo + kLeafKeys);
     top = hi + kLeafKeys;
-    occ = (uint32_t*)(top + kLeafKeys);
-    hist = occ + kLeafKeys / 32;
+    occ = (uint8_t*)(top + kLeafKeys);
+    hist = (uint32_t*)(occ + kLeafKeys);
     start = hist + kDigits;
     rowcnt = start + 2 * (kDigits + 1);
     scan = rowcnt + 256;
     misc = scan + kHeavyThreads / 64 + 1;
   }
   static constexpr size_t bytes() {
-    return (size_t)kLeafKeys * 24 + 4 * ((size_t)kLeafKeys / 32 + kDigits + 2 * (kDigits + 1) + 256 +
-                                         kHeavyThreads / 64 + 1 + 4);
+    return (size_t)kLeafKeys * 25 + 4 * ((size_t)kDigits + 2 * (kDigits + 1) + 256 + kHeavyThreads / 64 + 1 + 4);
   }
 };
 
@@ -1337,7 +1322,7 @@ __device__ void heavy_split(const HeavySmem& sm, const uint32_t* skey, const V* 
 __device__ __forceinline__ void heavy_normalise(const HeavySmem& sm) {
   constexpr unsigned long long M48 = (1ull << 48) - 1;
   for (int h = threadIdx.x; h < kLeafKeys; h += kHeavyThreads) {
-    if (!((sm.occ[h >> 5] >> (h & 31)) & 1u)) continue;
+    if (!sm.occ[h]) continue;
     const unsigned long long l = sm.lo[h];
     const long long x = sm.hi[h] + (long long)(l >> 48);
     sm.lo[h] = l & M48;
@@ -1367,7 +1352,7 @@ __device__ uint32_t heavy_leaf(const HeavySmem& sm, const uint32_t* key, const V
       if (ok && !((m >> lane) & 1ull)) {
         atomicAdd(&sm.lo[h], (unsigned long long)c0);
         atomicAdd((unsigned long long*)&sm.hi[h], (unsigned long long)c1);
-        atomicOr(&sm.occ[h >> 5], 1u << (h & 31));
+        sm.occ[h] = 1;
       }
       if (m) {  // the hot lanes' chunks summed over the wave (64 chunks stay below 2^54)
         unsigned long long s0 = ((m >> lane) & 1ull) ? c0 : 0ull;
@@ -1380,7 +1365,7 @@ __device__ uint32_t heavy_leaf(const HeavySmem& sm, const uint32_t* key, const V
         if (lane == 0) {
           atomicAdd(&sm.lo[hot], s0);
           atomicAdd((unsigned long long*)&sm.hi[hot], (unsigned long long)s1);
-          atomicOr(&sm.occ[hot >> 5], 1u << (hot & 31));
+          sm.occ[hot] = 1;
         }
       }
     });
@@ -1391,32 +1376,39 @@ __device__ uint32_t heavy_leaf(const HeavySmem& sm, const uint32_t* key, const V
   // the occupied slots in order: kLeafKeys / kHeavyThreads consecutive slots per lane
   constexpr int PL = kLeafKeys / kHeavyThreads;
   const int h0 = threadIdx.x * PL;
-  const uint32_t bits = (sm.occ[h0 >> 5] >> (h0 & 31)) & ((1u << PL) - 1);
+  static_assert(PL == 4, "four slot flags per lane are read as one word");
+  const uint32_t fw = *(const uint32_t*)(sm.occ + h0);  // byte j: slot h0 + j
+  const uint32_t bits = (fw & 1u) | ((fw >> 7) & 2u) | ((fw >> 14) & 4u) | ((fw >> 21) & 8u);
   uint32_t total;
   uint32_t pos = u0 + block_scan_u32(__popc(bits), sm.scan, &total);
   const uint32_t cmask = (1u << colbits) - 1;
 #pragma unroll
   for (int j = 0; j < PL; ++j) {
-    if (!((bits >> j) & 1u)) continue;
+    const bool occ = (bits >> j) & 1u;
     const int h = h0 + j;
+    const uint32_t k = kmin + (uint32_t)h;
+    // entries per row: a range spans few rows, so the lanes of a wave mostly share one
+    uint32_t hot;
+    const uint64_t m = heavy_hot(k >> colbits, occ, hot);
+    if (occ && !((m >> lane) & 1ull)) atomicAdd(&sm.rowcnt[k >> colbits], 1u);
+    if (lane == 0 && m) atomicAdd(&sm.rowcnt[hot], (uint32_t)__popcll(m));
+    if (!occ) continue;
     // value = lo + hi 2^48 + top 2^96, lo and hi in [0, 2^48): as a 128-bit integer
     const unsigned long long l = sm.lo[h], x = (unsigned long long)sm.hi[h];
     const long long t = sm.top[h];
     const uint64_t qlo = l | (x << 48);
     const uint64_t qhi = (x >> 16) | ((uint64_t)t << 32);
     const V hv = from_fixed_as<V>(qlo, qhi, F);
-    const uint32_t k = kmin + (uint32_t)h;
     tcol[pos] = (int32_t)(k & cmask);
     tval[pos] = hv;
     if constexpr (RES) tres[pos] = fixed_residual<V>(qlo, qhi, F, hv);
-    atomicAdd(&sm.rowcnt[k >> colbits], 1u);
     sm.lo[h] = 0ull;
     sm.hi[h] = 0ll;
     sm.top[h] = 0ll;
     ++pos;
   }
   __syncthreads();
-  if (threadIdx.x < kLeafKeys / 32) sm.occ[threadIdx.x] = 0u;
+  if (threadIdx.x < kLeafKeys / 4) ((uint32_t*)sm.occ)[threadIdx.x] = 0u;
   heavy_sync();
   return total;
 }
@@ -1425,7 +1417,7 @@ __device__ uint32_t heavy_leaf(const HeavySmem& sm, const uint32_t* key, const V
 __device__ __forceinline__ int heavy_shift(uint32_t w) {
   if (w <= (uint32_t)kLeafKeys) return 0;
   const int bits = 32 - __clz(w - 1);  // keys need `bits` bits
-  return bits - 10 > 12 ? bits - 10 : 12;
+  return bits - 11 > 12 ? bits - 11 : 12;  // at most kDigits digits
 }
 
 // (the pair buffers alias the output, so they carry no __restrict__)
@@ -1446,7 +1438,7 @@ __global__ __launch_bounds__(kHeavyThreads) void k_pass3_heavy(uint32_t* ikey, V
     sm.hi[h] = 0ll;
     sm.top[h] = 0ll;
   }
-  if (threadIdx.x < kLeafKeys / 32) sm.occ[threadIdx.x] = 0u;
+  if (threadIdx.x < kLeafKeys / 4) ((uint32_t*)sm.occ)[threadIdx.x] = 0u;
   const int F = 1117 - (int)*emax;
   int32_t* const tcol = (int32_t*)akey;
   for (uint32_t it = blockIdx.x; it < n_over; it += gridDim.x) {
@@ -1529,6 +1521,7 @@ __global__ __launch_bounds__(kHeavyThreads) void k_pass3_heavy(uint32_t* ikey, V
 }
 
 // ------------------------------------------------------------------------- final
+constexpr uint32_t kFinalWave = 4096;  // entries one wavefront of k_final copies
 // One wavefront per sub-bucket g: its entries copied to their final place ubase[g],
 // its rows' row_ptr = ubase[g] + local row offset.
 // GROUPED (running sums of a grouped build): also each entry's residual (tres -> res)
@@ -1548,7 +1541,7 @@ __global__ __launch_bounds__(256) void k_final(const uint32_t* __restrict__ sbb,
   const uint32_t base = ubase[g], U = ubase[g + 1] - base;
   const int64_t r0 = g << s2;
   const int R = (int)min((int64_t)1 << s2, n_node - r0);
-  if (nnz <= cap) {
+  if (nnz <= cap && U <= kFinalWave) {  // (larger: a heavy sub-bucket, k_final_heavy)
     const uint32_t src = sbb[g];
     for (uint32_t f = lane; f < U; f += 64) {
       col_idx[base + f] = tcol[src + f];
@@ -1561,11 +1554,57 @@ __global__ __launch_bounds__(256) void k_final(const uint32_t* __restrict__ sbb,
         for (uint32_t k = rowoff[r0 + r]; k < k1; ++k) rows[base + k] = (int32_t)(r0 + r);
       }
     }
-  } else if (g == 0 && lane == 0) {
+  } else if (nnz > cap && g == 0 && lane == 0) {
     raise_flag(status, KB_F_CAPACITY);
   }
   for (int r = lane; r < R; r += 64) row_ptr[r0 + r] = (int32_t)(base + rowoff[r0 + r]);
   if (g == nsub - 1 && lane == 0) row_ptr[n_node] = (int32_t)nnz;
+}
+
+// The entries of the sub-buckets k_final leaves (more than kFinalWave: only a heavy
+// sub-bucket, listed by pass 3, can hold more than a pass-3 table), copied by all the
+// workgroups of the grid in chunks of 1024; with GROUPED each entry's row is found by a
+// binary search of the sub-bucket's row offsets.
+template <typename V, bool GROUPED = false>
+__global__ __launch_bounds__(256) void k_final_heavy(const uint32_t* __restrict__ sbb, const uint32_t* __restrict__ ubase,
+                                                     const int32_t* __restrict__ tcol, const V* __restrict__ tval,
+                                                     const V* __restrict__ tres, const uint32_t* __restrict__ rowoff,
+                                                     int s2, int64_t n_node, int64_t nsub,
+                                                     const uint32_t* __restrict__ ov_list,
+                                                     const uint32_t* __restrict__ ov_count,
+                                                     int32_t* __restrict__ col_idx, V* __restrict__ vals,
+                                                     V* __restrict__ res, int32_t* __restrict__ rows, int64_t cap) {
+  const uint32_t n_over = *ov_count;
+  if (n_over == 0 || (int64_t)ubase[nsub] > cap) return;
+  for (uint32_t it = 0; it < n_over; ++it) {
+    const int64_t g = ov_list[it];
+    const uint32_t base = ubase[g], U = ubase[g + 1] - base;
+    if (U <= kFinalWave) continue;
+    const uint32_t src = sbb[g];
+    const int64_t r0 = g << s2;
+    const int R = (int)min((int64_t)1 << s2, n_node - r0);
+    for (uint32_t c = blockIdx.x * 1024u; c < U; c += gridDim.x * 1024u) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const uint32_t f = c + j * 256 + threadIdx.x;
+        if (f >= U) continue;
+        col_idx[base + f] = tcol[src + f];
+        vals[base + f] = tval[src + f];
+        if constexpr (GROUPED) {
+          res[base + f] = tres[src + f];
+          int lo = 0, hi = R - 1;  // last row whose first entry is at or before f
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (rowoff[r0 + mid] <= f)
+              lo = mid;
+            else
+              hi = mid - 1;
+          }
+          rows[base + f] = (int32_t)(r0 + lo);
+        }
+      }
+    }
+  }
 }
 
 }  // namespace kb
