@@ -410,19 +410,19 @@ int launch_pass3(const Plan& p, uint32_t* key2, V* val2, uint32_t* sbb, uint32_t
   uint32_t* ov_count = emax + 1;
   switch (p.ht) {
     case 512:
-      k_pass3<V, 512, RES><<<g3, 256, 0, s>>>(key2, val2, sbb, p.s2, p.colbits, p.nn, emax, tcol, tval, tres, rowoff,
+      k_pass3<V, 512, RES><<<g3, 256, (size_t)12 << p.s2, s>>>(key2, val2, sbb, p.s2, p.colbits, p.nn, emax, tcol, tval, tres, rowoff,
                                               usub, ov_list, ov_count);
       break;
     case 1024:
-      k_pass3<V, 1024, RES><<<g3, 256, 0, s>>>(key2, val2, sbb, p.s2, p.colbits, p.nn, emax, tcol, tval, tres,
+      k_pass3<V, 1024, RES><<<g3, 256, (size_t)12 << p.s2, s>>>(key2, val2, sbb, p.s2, p.colbits, p.nn, emax, tcol, tval, tres,
                                                rowoff, usub, ov_list, ov_count);
       break;
     case 2048:
-      k_pass3<V, 2048, RES><<<g3, 256, 0, s>>>(key2, val2, sbb, p.s2, p.colbits, p.nn, emax, tcol, tval, tres,
+      k_pass3<V, 2048, RES><<<g3, 256, (size_t)12 << p.s2, s>>>(key2, val2, sbb, p.s2, p.colbits, p.nn, emax, tcol, tval, tres,
                                                rowoff, usub, ov_list, ov_count);
       break;
     default:
-      k_pass3<V, 4096, RES><<<g3, 256, 0, s>>>(key2, val2, sbb, p.s2, p.colbits, p.nn, emax, tcol, tval, tres,
+      k_pass3<V, 4096, RES><<<g3, 256, (size_t)12 << p.s2, s>>>(key2, val2, sbb, p.s2, p.colbits, p.nn, emax, tcol, tval, tres,
                                                rowoff, usub, ov_list, ov_count);
       break;
   }

@@ -1025,18 +1025,21 @@ __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* _
                                                uint32_t* __restrict__ ov_list, uint32_t* __restrict__ ov_count) {
   constexpr int NT = 256, PER = 8;
   // once summed, each slot's value (and residual) is kept in place of its low chunk sum,
-  // which frees the high chunk sums for the columns grouped by row (one array fewer, six
-  // workgroups per CU at 1024 slots); a double with its double residual needs both words
+  // which frees the high chunk sums for the columns grouped by row (one array fewer); a
+  // double with its double residual needs both words.  The per-row arrays are sized by
+  // the sub-bucket's rows at launch and the columns are grouped by row through cursors
+  // (no per-slot index within the row): 22.4 KB at 1024 slots, seven workgroups per CU
   constexpr bool kSepCols = RES && sizeof(V) == 8;
   __shared__ uint32_t s_key[HT];
   __shared__ unsigned long long s_lo[HT];  // sum of low 48-bit chunks, then value (+ residual)
   __shared__ unsigned long long s_hi[HT];  // sum of signed high chunks, then the columns
   __shared__ uint16_t s_slot[HT];  // occupied slots, in insertion order
-  __shared__ uint16_t s_wi[HT];    // each occupied slot's index within its row
   __shared__ uint32_t s_sep[kSepCols ? HT : 1];
-  __shared__ uint32_t s_rc[256];   // entries per row
-  __shared__ uint32_t s_ro[256];   // row offsets
   __shared__ uint32_t s_over, s_nu;
+  extern __shared__ uint32_t s_rows[];  // 3 << s2 words: entries per row, row offsets, cursors
+  uint32_t* const s_rc = s_rows;
+  uint32_t* const s_ro = s_rows + (1 << s2);
+  uint32_t* const s_cur = s_rows + (2 << s2);
   uint32_t* const s_lcol = kSepCols ? s_sep : (uint32_t*)s_hi;  // columns of the slots, grouped by row
 
   const int64_t g = blockIdx.x;
@@ -1090,7 +1093,7 @@ __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* _
               k = atomicCAS(&s_key[h], kEmptyKey, key);
               if (k == kEmptyKey) {  // inserted: record the slot and its place in its row
                 s_slot[atomicAdd(&s_nu, 1u)] = (uint16_t)h;
-                s_wi[h] = (uint16_t)atomicAdd(&s_rc[key >> colbits], 1u);
+                atomicAdd(&s_rc[key >> colbits], 1u);
                 break;
               }
               if (k == key) break;
@@ -1158,7 +1161,10 @@ __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* _
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int r = lane * 4 + k;
-      if (r < RB) s_ro[r] = run;
+      if (r < RB) {
+        s_ro[r] = run;
+        s_cur[r] = run;
+      }
       run += v[k];
     }
   }
@@ -1166,7 +1172,7 @@ __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* _
   for (uint32_t f = threadIdx.x; f < U; f += NT) {
     const uint32_t h = s_slot[f];
     const uint32_t k = s_key[h];
-    s_lcol[s_ro[k >> colbits] + s_wi[h]] = k & cmask;
+    s_lcol[atomicAdd(&s_cur[k >> colbits], 1u)] = k & cmask;
   }
   __syncthreads();
   for (uint32_t f = threadIdx.x; f < U; f += NT) {
