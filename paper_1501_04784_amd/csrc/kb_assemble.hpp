@@ -1082,32 +1082,17 @@ __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* _
       for (int u = 0; u < PER; ++u) {
         if (i0 + u * NT + threadIdx.x >= end) continue;
         const uint32_t key = kk[u];
+        // one compare-and-swap per probe: it returns the empty marker when this lane
+        // took the slot, the key when the entry was there already, else another key
         uint32_t h = slot_hash<HT>(key);
-        uint32_t k = s_key[h];
-        bool found = true;
-        if (k != key) {  // rare: not at its home slot yet
-          int probes = 0;
+        uint32_t k = atomicCAS(&s_key[h], kEmptyKey, key);
+        int probes = 0;
 #pragma unroll 1
-          while (true) {
-            if (k == kEmptyKey) {
-              k = atomicCAS(&s_key[h], kEmptyKey, key);
-              if (k == kEmptyKey) {  // inserted: record the slot and its place in its row
-                s_slot[atomicAdd(&s_nu, 1u)] = (uint16_t)h;
-                atomicAdd(&s_rc[key >> colbits], 1u);
-                break;
-              }
-              if (k == key) break;
-            }
-            if (++probes >= HT) {
-              found = false;
-              break;
-            }
-            h = (h + 1) & (HT - 1);
-            k = s_key[h];
-            if (k == key) break;
-          }
+        while (k != kEmptyKey && k != key && ++probes < HT) {
+          h = (h + 1) & (HT - 1);
+          k = atomicCAS(&s_key[h], kEmptyKey, key);
         }
-        if (!found) {
+        if (k != kEmptyKey && k != key) {  // the table is full
           s_over = 1;
           continue;
         }
@@ -1124,7 +1109,17 @@ __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* _
     if (threadIdx.x == 0) ov_list[atomicAdd(ov_count, 1u)] = (uint32_t)g;
     return;
   }
-  // order the U entries by (row, col): the row counts (taken at insertion) scanned by one
+  // list the occupied slots and count the entries of each row (once per entry here
+  // rather than on the insertion path of every pair)
+  for (int h = threadIdx.x; h < HT; h += NT) {
+    const uint32_t k = s_key[h];
+    if (k != kEmptyKey) {
+      s_slot[atomicAdd(&s_nu, 1u)] = (uint16_t)h;
+      atomicAdd(&s_rc[k >> colbits], 1u);
+    }
+  }
+  __syncthreads();
+  // order the U entries by (row, col): the row counts scanned by one
   // wave while the others round each sum to its value, the entries grouped by row, then
   // ranked by column within their row
   const uint32_t U = s_nu;
