@@ -139,20 +139,21 @@ __device__ __forceinline__ void split48(uint64_t lo, uint64_t hi, uint64_t& c0, 
 // formed in FP64 arithmetic, where every step is exact: v 2^F only moves the exponent
 // (|q| < 2^95; a result below 2^-1022 truncates to 0 either way), trunc and floor give
 // integers, and c1 = floor(q / 2^48), c0 = q - c1 2^48 in [0, 2^48) are multiples of
-// q's last bit below 2^53 of it.  Each is then converted through two 32-bit halves.
-// The same integers as split48 of to_fixed's q, without forming the 128-bit integer and
-// without branches.
+// q's last bit below 2^53 of it.  Each integer then becomes a 64-bit word by an exact
+// FP64 addition: c0 + 2^52 and c1 + 1.5 2^52 (|c1| < 2^47) lie in [2^52, 2^53), where
+// the spacing is 1, so their bit patterns are those of the constants plus the integer
+// (two's complement for a negative c1), and the constants' low 32 bits are zero: one
+// 32-bit subtraction from the high word leaves the integer.  The same integers as
+// split48 of to_fixed's q, without forming the 128-bit integer and without branches.
 __device__ __forceinline__ void to_chunks(double v, int F, uint64_t& c0, int64_t& c1) {
   const double d = isfinite(v) ? v : 0.0;
   const double q = trunc(ldexp(d, F));
   const double h = floor(ldexp(q, -48));
-  const double l = fma(h, -0x1p48, q);     // [0, 2^48)
-  const double lh = floor(ldexp(l, -32));  // [0, 2^16)
-  const double ll = fma(lh, -0x1p32, l);   // [0, 2^32)
-  c0 = ((uint64_t)(uint32_t)lh << 32) | (uint64_t)(uint32_t)ll;
-  const double hh = floor(ldexp(h, -32));  // |hh| < 2^15
-  const double hl = fma(hh, -0x1p32, h);   // [0, 2^32)
-  c1 = (int64_t)(((uint64_t)(int64_t)(int32_t)hh << 32) | (uint64_t)(uint32_t)hl);
+  const double l = fma(h, -0x1p48, q);  // [0, 2^48)
+  const uint64_t bl = (uint64_t)__double_as_longlong(l + 0x1p52);
+  const uint64_t bh = (uint64_t)__double_as_longlong(h + 0x1.8p52);
+  c0 = bl - 0x4330000000000000ull;
+  c1 = (int64_t)(bh - 0x4338000000000000ull);
 }
 __device__ __forceinline__ void to_chunks(float v, int F, uint64_t& c0, int64_t& c1) {
   to_chunks((double)v, F, c0, c1);  // a float is exactly a double
@@ -1066,21 +1067,25 @@ __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* _
   // the range; the empty asm keeps the compiler from sinking a load into the branch
   // that first uses it)
   if (!s_over) {
-    for (uint32_t i0 = beg; i0 < end; i0 += PER * NT) {
+    // (offsets from the sub-bucket's first pair: below 2^16 here)
+    const uint32_t n = end - beg;
+    const uint32_t* const kp = ikey + beg;
+    const V* const vp = ival + beg;
+    for (uint32_t j0 = 0; j0 < n; j0 += PER * NT) {
       uint32_t kk[PER];
       V vv[PER];
 #pragma unroll
       for (int u = 0; u < PER; ++u) {
-        const uint32_t i = i0 + u * NT + threadIdx.x;
-        const uint32_t ic = i < end ? i : beg;
-        kk[u] = ikey[ic];
-        vv[u] = ival[ic];
+        const uint32_t j = j0 + u * NT + threadIdx.x;
+        const uint32_t jc = (j < n ? j : 0u) & 0xffffu;
+        kk[u] = kp[jc];
+        vv[u] = vp[jc];
       }
 #pragma unroll
       for (int u = 0; u < PER; ++u) asm volatile("" : "+v"(kk[u]), "+v"(vv[u]));
 #pragma unroll
       for (int u = 0; u < PER; ++u) {
-        if (i0 + u * NT + threadIdx.x >= end) continue;
+        if (j0 + u * NT + threadIdx.x >= n) continue;
         const uint32_t key = kk[u];
         // one compare-and-swap per probe: it returns the empty marker when this lane
         // took the slot, the key when the entry was there already, else another key
