@@ -141,8 +141,9 @@ def parse():
     ap.add_argument("--bucket-bits", type=int, default=0, help="tuning: log2 rows per first-level bucket")
     ap.add_argument("--sub-bits", type=int, default=0, help="tuning: log2 rows per sub-bucket")
     ap.add_argument("--seg-pairs", type=int, default=0, help="tuning: pairs per sub-bucket partition segment")
+    ap.add_argument("--table-slots", type=int, default=0, help="tuning: pass-3 hash-table slots per sub-bucket")
     ap.add_argument("--no-tune", action="store_true",
-                    help="batch workload: time only the built-in tuning (no tuning search / cache lookup)")
+                    help="batch and t2 workloads: time only the built-in tuning (no tuning search / cache lookup)")
     ap.add_argument("--tune-cache", default=None, help="JSON cache of tuning choices (default: KBUILD_TUNE_CACHE "
                                                        "or ~/.cache/kbuild/tuning.json)")
     return ap.parse_args()
@@ -479,13 +480,17 @@ def main():
     print(f"[bench] {m.n_elem} elements, {m.n_node} nodes on device; timing {prec}", file=sys.stderr, flush=True)
 
     tuning = kb.Tuning(block=args.block, bucket_bits=args.bucket_bits, sub_bits=args.sub_bits,
-                       seg_pairs=args.seg_pairs)
+                       seg_pairs=args.seg_pairs, table_slots=args.table_slots)
     tune = None
-    if cid == 4 and not args.no_tune and tuning == kb.Tuning():
-        # the batch takes the tuning search's choice (cached per architecture, element,
-        # precision and size class); the built-in choice is timed beside it below
+    if cid in (4, 7) and not args.no_tune and tuning == kb.Tuning() and groups <= 1:
+        # the batch and the naturally numbered 27M bricks take the tuning search's choice
+        # (cached per architecture, element, precision and size class); the built-in
+        # choice is timed beside it below
         t0 = time.perf_counter()
-        tuning, entry = kb.tune_batch(mesh_dev, prec, cache_path=args.tune_cache)
+        if cid == 4:
+            tuning, entry = kb.tune_batch(mesh_dev, prec, cache_path=args.tune_cache)
+        else:
+            tuning, entry = kb.tune_build(*mesh_dev, m.elem, prec, op=args.op, cache_path=args.tune_cache)
         tune = {"tuning": entry["tuning"], "source": entry["source"], "key": entry["key"],
                 "search_s": time.perf_counter() - t0, "candidates_timed": entry.get("candidates_timed")}
         print(f"[bench] tuning ({entry['source']}): {tuning}", file=sys.stderr, flush=True)
@@ -511,7 +516,7 @@ def main():
                    "n_elem": m.n_elem, "n_node": m.n_node, "nnz": nnz, "precision": prec,
                    "fp64_fallback_elements": n_fallback, "parallelism": "single GPU",
                    "tuning": {"block": tuning.block, "bucket_bits": tuning.bucket_bits, "sub_bits": tuning.sub_bits,
-                              "seg_pairs": tuning.seg_pairs},
+                              "seg_pairs": tuning.seg_pairs, "table_slots": tuning.table_slots},
                    "groups": groups if groups > 1 else 1},
         "path_hbm_frac": ab["path"] / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
     }

@@ -62,7 +62,7 @@
 extern "C" {
 #endif
 
-#define KB_VERSION 3
+#define KB_VERSION 4
 
 /* element types (value = nodes per element) */
 #define KB_HEX8 8
@@ -135,7 +135,12 @@ typedef struct {
   int32_t seg_pairs;       /* pairs per segment of the sub-bucket partition: 4096 or 8192
                               (0 = from the mesh shape: 8192 for tetrahedra whose short
                               segments would give fewer than 16 pairs per sub-bucket)   */
-  int32_t reserved;        /* must be 0                                                */
+  int32_t table_slots;     /* slots of the hash table that sums one sub-bucket's pairs
+                              in pass 3: 512, 1024, 2048 or 4096 (0 = about four per
+                              expected distinct entry).  Fewer slots than that fit more
+                              rows per sub-bucket in the same local memory; a
+                              sub-bucket whose entries do not fit goes to the slower
+                              overflow path, with the same result                       */
 } kb_tuning;
 
 /*

@@ -80,10 +80,11 @@ class Tuning:
     fb_tau: float = 0.0
     sub_bits: int = 0
     seg_pairs: int = 0
+    table_slots: int = 0
 
     def to_c(self, events=None) -> KbTuning:
         return KbTuning(int(self.block), int(self.bucket_bits), float(self.fb_tau), int(self.sub_bits), events,
-                        int(self.seg_pairs), 0)
+                        int(self.seg_pairs), int(self.table_slots))
 
 
 def plan(elem: int, n_elem: int, n_node: int, prec="fp64", tuning: Tuning | None = None, op="stiffness",
@@ -624,6 +625,25 @@ def tune_batch(batch: Batch, prec="fp32fb64", cache_path: str | None = None, ref
     return autotune.tuned("batch", batch.elem, prec, n_pairs, make_run, cache_path=cache_path, refresh=refresh)
 
 
+def tune_build(conn, coords, coef, elem: int, prec="fp32fb64", op="stiffness", cache_path: str | None = None,
+               refresh: bool = False):
+    """(Tuning, cache entry) for builds of one mesh of this shape: the cached choice for
+    its (architecture, operator, element, precision, size class), else a timed search
+    over the tile, bucket, sub-bucket, segment and table knobs on this mesh, stored in
+    the JSON cache (``autotune``).  Every candidate gives the same matrix bit for bit."""
+    from . import autotune
+
+    n_elem, n_node = int(conn.shape[0]), int(coords.shape[0])
+    n_pairs = n_elem * elem * (elem + 1) // 2
+
+    def make_run(t):
+        b = Builder(elem, n_elem, n_node, prec, t, device=conn.device, op=op)
+        return lambda: b.run(conn, coords, coef)
+
+    kind = "build" if _op(op) == KB_OP_STIFFNESS else "build-mass"
+    return autotune.tuned(kind, elem, prec, n_pairs, make_run, cache_path=cache_path, refresh=refresh)
+
+
 def build_lower_csr_batched(meshes, elem: int, prec="fp32fb64", tuning: Tuning | None = None, check=True,
                             allow_flags: int = 0, device="cuda") -> list:
     """Build each mesh of [(conn, coords, coef), ...] (mesh-local ids) in one batched call."""
@@ -637,5 +657,5 @@ __all__ = ["Builder", "BatchBuilder", "Batch", "GroupedBuilder", "StreamedGroupe
            "build_lower_csr_batched", "assemble_lower_csr", "integrate_lower", "adjoint_lower", "AdjointBuilder",
            "lower_csr_values",
            "pack_batch", "plan", "plan_batched",
-           "tune_batch", "status_string", "version", "value_dtype", "STAGE_NAMES", "KB_N_STAGES",
+           "tune_batch", "tune_build", "status_string", "version", "value_dtype", "STAGE_NAMES", "KB_N_STAGES",
            "KB_HEX8", "KB_TET4", "KB_FP64", "KB_FP32", "KB_FP32_FB64", "KB_OP_STIFFNESS", "KB_OP_MASS"]

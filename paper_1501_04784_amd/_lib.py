@@ -58,7 +58,7 @@ class KbTuning(ctypes.Structure):
         ("sub_bits", ctypes.c_int32),
         ("stage_events", ctypes.c_void_p),
         ("seg_pairs", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("table_slots", ctypes.c_int32),
     ]
 
 

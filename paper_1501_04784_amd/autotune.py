@@ -3,12 +3,17 @@
 The knobs are those of ``kb_tuning``: the pass-1 element tile (elements per workgroup,
 hence elements per wavefront), the first-level bucket width and the sub-bucket width
 of the two partition passes (the widths of the "radix" digits the pairs are split on),
-and the segment length of the sub-bucket partition (pairs per chunk of a bucket).
+the segment length of the sub-bucket partition (pairs per chunk of a bucket), and the
+slots of the hash table that sums a sub-bucket (fewer slots per entry let wider
+sub-buckets keep the same local memory; too few send sub-buckets to the overflow path).
 Every candidate runs the same kernels on the same inputs, so any valid candidate
 gives the same matrix bit for bit; the search only times them.
 
 The search is coordinate descent from the built-in choice: each knob in turn is set to
-each of its values with the others held, the fastest kept, for two sweeps.  Results are
+each of its values with the others held, the fastest kept, for up to three sweeps.  The
+sub-bucket width and the table size are one coordinate (every pair of their values):
+a wider sub-bucket pays only with a table that still lets as many workgroups share a
+compute unit, so neither moves alone.  Results are
 cached per (device architecture, build kind, element, precision, size class), the size
 class being log2 of the number of lower pairs rounded to an integer, in a JSON file
 (``KBUILD_TUNE_CACHE``, else ``~/.cache/kbuild/tuning.json``).
@@ -32,12 +37,20 @@ TILES = {(4, False): (1024, 512), (4, True): (768, 384), (8, False): (256, 128),
 BUCKET_BITS = (0, 12, 14, 16)
 SUB_BITS = (0, 3, 4, 5)
 SEG_PAIRS = (0, 4096, 8192)
+TABLE_SLOTS = (0, 512, 1024, 2048)
 
 
 def axes(elem: int, prec) -> dict:
-    """Values of each knob (0 = the library's own choice from the mesh shape)."""
+    """Values of each coordinate of the search (0 = the library's own choice from the
+    mesh shape); a coordinate named by a tuple of knobs takes tuples of their values."""
     return {"block": (0,) + TILES[(int(elem), _prec(prec) == KB_FP64)], "bucket_bits": BUCKET_BITS,
-            "sub_bits": SUB_BITS, "seg_pairs": SEG_PAIRS}
+            ("sub_bits", "table_slots"): tuple((s, t) for s in SUB_BITS for t in TABLE_SLOTS),
+            "seg_pairs": SEG_PAIRS}
+
+
+def _with(t: Tuning, knob, value) -> Tuning:
+    fields = dict(zip(knob, value)) if isinstance(knob, tuple) else {knob: value}
+    return Tuning(**{**asdict(t), **fields})
 
 
 def arch() -> str:
@@ -93,7 +106,7 @@ def time_ms(run, reps: int = 3, warmup: int = 1) -> float:
     return e0.elapsed_time(e1) / reps
 
 
-def search(make_run, elem: int, prec, reps: int = 3, warmup: int = 1, sweeps: int = 2):
+def search(make_run, elem: int, prec, reps: int = 3, warmup: int = 1, sweeps: int = 3):
     """Coordinate descent over ``axes``.  ``make_run(tuning)`` returns a callable that
     enqueues one build with that tuning, or raises KBuildError (or ValueError) when the
     tuning is not valid for the shape.  Returns (best Tuning, {Tuning: ms})."""
@@ -115,7 +128,7 @@ def search(make_run, elem: int, prec, reps: int = 3, warmup: int = 1, sweeps: in
         moved = False
         for knob, values in axes(elem, prec).items():
             for v in values:
-                t = Tuning(**{**asdict(best), knob: v})
+                t = _with(best, knob, v)
                 if cost(t) < cost(best):
                     best, moved = t, True
         if not moved:

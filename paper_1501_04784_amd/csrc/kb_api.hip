@@ -125,7 +125,9 @@ int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p, int dof 
     if (tu->bucket_bits && tu->sub_bits && tu->sub_bits > tu->bucket_bits) return KB_EINVAL;
     bucket_bits = tu->bucket_bits;
     sub_bits = tu->sub_bits;
-    if ((tu->seg_pairs != 0 && tu->seg_pairs != kSeg && tu->seg_pairs != kSegLong) || tu->reserved != 0)
+    if (tu->seg_pairs != 0 && tu->seg_pairs != kSeg && tu->seg_pairs != kSegLong) return KB_EINVAL;
+    if (tu->table_slots != 0 && (tu->table_slots < kHTMin || tu->table_slots > kHTMax ||
+                                 (tu->table_slots & (tu->table_slots - 1))))
       return KB_EINVAL;
   }
   // sub-buckets: about a third of the pass-3 hash table of distinct entries on average;
@@ -180,6 +182,7 @@ int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p, int dof 
       ++p->s1;
     }
   }
+  if (tu && tu->table_slots) p->ht = tu->table_slots;
   p->p2 = 1 << (p->s1 - p->s2);
   p->nb = (int)div_up(p->nn, (int64_t)1 << p->s1);
   p->nsub = (int64_t)p->nb * p->p2;

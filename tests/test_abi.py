@@ -41,7 +41,7 @@ def test_struct_layout():
     assert ctypes.sizeof(KbMesh) == 48
     assert KbMesh.conn.offset == 24 and KbMesh.coef.offset == 40
     assert ctypes.sizeof(KbTuning) == 32 and KbTuning.stage_events.offset == 16
-    assert KbTuning.seg_pairs.offset == 24 and KbTuning.reserved.offset == 28
+    assert KbTuning.seg_pairs.offset == 24 and KbTuning.table_slots.offset == 28
 
 
 def _plan(elem, nel, nn, prec=0, tuning=None):
@@ -55,7 +55,7 @@ def _plan(elem, nel, nn, prec=0, tuning=None):
 
 def test_version_and_strings():
     L = _lib.lib()
-    assert L.kb_version() == 3
+    assert L.kb_version() == 4
     assert L.kb_status_string(0) == b"ok"
     assert L.kb_status_string(-3) == b"workspace too small"
     assert L.kb_status_string(16) == b"nnz exceeds capacity"
@@ -110,7 +110,10 @@ def test_plan_errors():
     assert _plan(8, 10, 10, tuning=KbTuning(0, 20, 0.0, 2, None))[0] == _lib.KB_EINVAL  # > 1024 sub-buckets
     assert _plan(8, 10, 10, tuning=KbTuning(512, 10, 8.0, 4, None))[0] == 0
     assert _plan(8, 10, 10, tuning=KbTuning(0, 0, 0.0, 0, None, 2048, 0))[0] == _lib.KB_EINVAL  # segment length
-    assert _plan(8, 10, 10, tuning=KbTuning(0, 0, 0.0, 0, None, 0, 1))[0] == _lib.KB_EINVAL  # reserved
+    for slots in (1, 256, 768, 8192, -1024):  # table slots: a power of two in [512, 4096]
+        assert _plan(8, 10, 10, tuning=KbTuning(0, 0, 0.0, 0, None, 0, slots))[0] == _lib.KB_EINVAL
+    for slots in (512, 1024, 2048, 4096):
+        assert _plan(4, 1000, 300, tuning=KbTuning(0, 0, 0.0, 5, None, 0, slots))[0] == 0
     assert _plan(8, 10, 10, tuning=KbTuning(0, 0, 0.0, 0, None, 8192, 0))[0] == 0
     assert _plan(4, 10, 10, tuning=KbTuning(0, 0, 0.0, 0, None, 4096, 0))[0] == 0
 

@@ -49,7 +49,7 @@ def test_every_candidate_plans_or_is_refused_cleanly():
             for knob, values in autotune.axes(elem, prec).items():
                 for v in values:
                     try:
-                        kb.plan(elem, 50_000, 60_000, prec, kb.Tuning(**{knob: v}))
+                        kb.plan(elem, 50_000, 60_000, prec, autotune._with(kb.Tuning(), knob, v))
                     except kb.KBuildError as e:
                         assert "invalid argument" in str(e)
 
@@ -75,3 +75,15 @@ def test_cache_round_trip(fake_device, tmp_path):
     assert len(json.load(open(path))) == 3
     t3, e3 = autotune.tuned("batch", 8, "fp32fb64", 36 * 11_600_617, make_run, cache_path=path, refresh=True)
     assert e3["source"] == "search" and t3 == t1
+
+
+def test_joint_coordinate_finds_a_pair_that_neither_knob_finds_alone(fake_device):
+    """Sub-bucket width 5 pays only with 1024 table slots (each alone is slower than the
+    built-in choice): one coordinate over both reaches the pair."""
+    def cost(t: kb.Tuning) -> float:
+        if (t.sub_bits, t.table_slots) == (5, 1024):
+            return 0.5
+        return 1.0 + 0.5 * (t.sub_bits == 5) + 0.25 * (t.table_slots != 0)
+
+    best, _ = autotune.search(lambda t: (lambda: cost(t)), 8, "fp64")
+    assert (best.sub_bits, best.table_slots) == (5, 1024)

@@ -9,6 +9,8 @@
 * The same paths at sizes the oracle finishes in seconds: the half tiles (512 / 384
   elements) on a mesh with several tiles per workgroup, and a tuning that forces the
   long segments and 512 sub-buckets per bucket on a small mesh.
+* Pass-3 hash tables sized by hand, down to one slot per expected entry, and the tuning
+  search's choice for one mesh.
 """
 from __future__ import annotations
 
@@ -88,3 +90,45 @@ def test_long_segments_many_sub_buckets(prec):
     r = kb.build_lower_csr(*to_dev(m), m.elem, prec=prec, tuning=kb.Tuning(bucket_bits=14, sub_bits=5))
     ref = oracle.build_mesh(m)
     compare(m, r, ref[:3], prec)
+
+
+@pytest.mark.parametrize("cid,n,sub_bits,slots", [(3, 30, 5, 512), (3, 30, 4, 4096), (7, 40, 5, 1024), (7, 40, 6, 512)])
+def test_table_slots(cid, n, sub_bits, slots):
+    """The pass-3 table size set by hand, with wider sub-buckets: randomly numbered tets
+    with half-size tables (the last rows' sub-buckets, which hold about twice the
+    average entries, overflow to the heavy path), a table of 4096 slots, and naturally
+    numbered bricks at two and one slots per expected entry.  Every entry against the
+    oracle, and bit for bit the matrix of the default launch."""
+    m = meshgen.config_mesh(cid, n=n)
+    prec = "fp32fb64" if cid == 3 else "fp64"
+    say(f"[table-slots] cid={cid} n={n} sub_bits={sub_bits} slots={slots} nel={m.n_elem:,} {prec}")
+    dev = to_dev(m)
+    r = kb.build_lower_csr(*dev, m.elem, prec=prec, tuning=kb.Tuning(sub_bits=sub_bits, table_slots=slots))
+    d = kb.build_lower_csr(*dev, m.elem, prec=prec)
+    for x, y in zip(np_csr(r), np_csr(d)):
+        assert np.array_equal(x.view(np.uint8), y.view(np.uint8))
+    ref = oracle.build_mesh(m)
+    compare(m, r, ref[:3], prec)
+
+
+def test_tune_build_valid_cached_and_bit_equal(tmp_path):
+    """The tuning search on one naturally numbered brick mesh: the choice is valid for
+    the shape, stored in the JSON cache and read back from it, never slower than the
+    built-in choice in the search's own timing, and builds the same matrix bit for bit."""
+    m = meshgen.config_mesh(7, n=24)
+    dev = to_dev(m)
+    cache = str(tmp_path / "tuning.json")
+    t, entry = kb.tune_build(*dev, m.elem, "fp64", cache_path=cache)
+    say(f"[tune-build] chose {t} in {entry['ms']:.3f} ms (built-in {entry['default_ms']:.3f} ms, "
+        f"{entry['candidates_timed']} candidates timed)")
+    assert entry["source"] == "search" and entry["candidates_timed"] >= 4
+    assert entry["ms"] <= entry["default_ms"]
+    kb.plan(m.elem, m.n_elem, m.n_node, "fp64", t)  # valid
+    t2, entry2 = kb.tune_build(*dev, m.elem, "fp64", cache_path=cache)
+    assert entry2["source"] == "cache" and t2 == t
+    r = kb.build_lower_csr(*dev, m.elem, prec="fp64", tuning=t)
+    d = kb.build_lower_csr(*dev, m.elem, prec="fp64")
+    for x, y in zip(np_csr(r), np_csr(d)):
+        assert np.array_equal(x.view(np.uint8), y.view(np.uint8))
+    ref = oracle.build_mesh(m)
+    compare(m, r, ref[:3], "fp64")
