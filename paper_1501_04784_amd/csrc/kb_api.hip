@@ -327,6 +327,17 @@ int launch_pass1_block(const Plan& p, const kb_mesh* m, const void* klow, unsign
     KB_LAUNCH_CHECK();
     return KB_OK;
   }
+  if constexpr (NEN == 8 && !FROM_VALUES && P == Prec::F64) {
+    // bricks in FP64: two tiles per workgroup (two waves per SIMD while integrating)
+    auto kern = k_pass1_two<NEN, P, BLOCK, OP>;
+    if (!set_lds(kern, p.lds1)) return KB_EHIP;
+    kern<<<(unsigned)div_up(p.ntiles, 2), 2 * BLOCK, p.lds1, s>>>(
+        m->conn, (const double4*)(ws + p.o_coords4), m->coef, p.nel, p.nn, p.tau, p.s1, p.nb, p.ntiles,
+        (const uint32_t*)(ws + p.o_hist), (uint16_t*)(ws + p.o_row1), (uint32_t*)(ws + p.o_col1),
+        (V*)(ws + p.o_val1), (uint32_t*)(ws + p.o_emax), status);
+    KB_LAUNCH_CHECK();
+    return KB_OK;
+  }
   auto kern = [] {
     if constexpr (NEN == 4)
       return k_pass1_tet<P, FROM_VALUES, BLOCK, OP>;

@@ -474,6 +474,64 @@ __global__ __launch_bounds__(BLOCK) void k_pass1(const int32_t* __restrict__ con
   pass1_write(sm, n_items, s1, BLOCK, orow, ocol, oval);
 }
 
+// Bricks in FP64 from coordinates (one element per lane at the register limit): two
+// tiles per workgroup of 2 BLOCK lanes, so that each SIMD holds two waves while the
+// elements are gathered and integrated.  The two tiles are then counted, staged and
+// written one after the other through the one staging area (BLOCK elements' pairs).
+// Workgroup w takes tiles 2w and 2w + 1, XCD-contiguously as k_pass1.
+template <int NEN, Prec P, int BLOCK, Op OP = Op::Stiffness>
+__global__ __launch_bounds__(2 * BLOCK) void k_pass1_two(const int32_t* __restrict__ conn,
+                                                       const double4* __restrict__ coords4,
+                                                       const double* __restrict__ coef, int64_t n_elem, int64_t n_node,
+                                                       float tau, int s1, int nb, int64_t ntiles,
+                                                       const uint32_t* __restrict__ off1, uint16_t* __restrict__ orow,
+                                                       uint32_t* __restrict__ ocol,
+                                                       typename PrecTraits<P>::V* __restrict__ oval,
+                                                       uint32_t* __restrict__ emax, uint32_t* __restrict__ status) {
+  using V = typename PrecTraits<P>::V;
+  constexpr int T = ElemTraits<NEN>::T;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const Pass1Smem<V, 2 * BLOCK> sm(smem, BLOCK * T, nb);
+  const int64_t w = xcd_item(blockIdx.x, gridDim.x);
+  const int half = threadIdx.x >= BLOCK ? 1 : 0;
+  const int64_t e = (2 * w + half) * BLOCK + (threadIdx.x - half * BLOCK);
+  if (threadIdx.x == 0) *sm.emax = 0;
+  int32_t E[NEN];
+  bool valid = false;
+  if (e < n_elem) {
+    load_conn<NEN>(conn, e, E);
+    valid = check_conn<NEN>(E, n_node) == 0;
+  }
+  int r[NEN];
+  if (valid) node_ranks<NEN>(E, r);
+  uint32_t flags = 0, fb = 0;
+  V k[T];
+  if (valid) element_values<NEN, P, NodesPadded, OP>(NodesPadded{coords4}, coef, e, E, tau, k, &flags, &fb);
+  if (flags) raise_flag(status, flags);
+  if (fb) atomicAdd(&status[1], fb);
+  __syncthreads();
+  if (valid) atomicMax(sm.emax, values_emax<T>(k));
+  for (int h = 0; h < 2; ++h) {
+    const int64_t t = 2 * w + h;
+    if (t >= ntiles) break;
+    for (int b = threadIdx.x; b < nb; b += 2 * BLOCK) {
+      sm.cnt[b] = 0;
+      sm.base[b] = off1[t * nb + b];
+    }
+    __syncthreads();
+    uint32_t q[NEN];
+    const bool mine = valid && half == h;
+    if (mine) reserve_rows<NEN, 0>(sm.cnt, E, r, s1, q);
+    __syncthreads();
+    const uint32_t n_items = block_scan_array(sm.cnt, nb, sm.scan);
+    if (mine) pass1_stage<NEN>(sm, E, q, k, s1);
+    __syncthreads();
+    pass1_write(sm, n_items, s1, 2 * BLOCK, orow, ocol, oval);
+    __syncthreads();  // the staging area is reused by the next tile
+  }
+  if (threadIdx.x == 0 && *sm.emax) atomicMax(emax, *sm.emax);
+}
+
 // stage the pairs of rows R0 .. R0+3 of a brick (the lane's half of a lane pair)
 template <int R0, typename V, typename SM>
 __device__ __forceinline__ void pair_stage_half(const SM& sm, const int32_t (&E)[8], const uint32_t (&q)[4],
