@@ -74,15 +74,19 @@ def test_build_parity(name, prec):
     assert err <= TOL[prec]
 
 
+@pytest.mark.parametrize("nz", [11, 9])
 @pytest.mark.parametrize("op", ["stiffness", "mass"])
 @pytest.mark.parametrize("block", [256, 192, 128])
-def test_fp64_brick_tiles(block, op):
+def test_fp64_brick_tiles(block, op, nz):
     """Every FP64 brick pass-1 tile (256 by default, 192 where many buckets crowd the LDS,
     128 the half tile), forced through the tuning, against the oracle: a randomly numbered
-    box spanning several tiles with a ragged last one."""
-    m = meshgen.box_mesh(8, 23, 19, 11, jitter=0.25, coef=(0.1, 10), permute_nodes=True, permute_elems=True,
+    box spanning several tiles with a ragged last one.  Workgroups take two tiles each; the
+    two boxes (4807 and 3933 bricks) give every tile size both an odd tile count (a last
+    workgroup with one tile) and an even one."""
+    m = meshgen.box_mesh(8, 23, 19, nz, jitter=0.25, coef=(0.1, 10), permute_nodes=True, permute_elems=True,
                          seed=77)
-    say(f"[tile] block={block} {op} nel={m.n_elem}")
+    ntiles = -(-m.n_elem // block)
+    say(f"[tile] block={block} {op} nel={m.n_elem} tiles={ntiles}")
     conn, coords, coef = to_dev(m)
     r = kb.build_lower_csr(conn, coords, coef, 8, prec="fp64", op=op, tuning=kb.Tuning(block=block))
     rp, col, val = np_csr(r)
