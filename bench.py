@@ -528,8 +528,8 @@ def main():
         dom = max(SINGLE_KERNEL_STAGES, key=lambda k: stages[k])
         kernel = SINGLE_KERNEL_STAGES[dom]
         if dom == "integrate":  # the pass-1 variant the build launches
-            kernel = "k_pass1_tet" if m.elem == 4 else ("k_pass1_pair" if prec != "fp64" and args.op == "stiffness"
-                                                        else "k_pass1")
+            kernel = "k_pass1_tet" if m.elem == 4 else ("k_pass1_two" if prec == "fp64" else
+                                                        "k_pass1_pair" if args.op == "stiffness" else "k_pass1")
         achieved = ab[dom] / (stages[dom] * 1e-3) / 1e9
         traffic = stored_traffic(kernel, args.workload, prec)
         out["roofline"] = {"bound": "hbm", "kernel": kernel, "stage": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
