@@ -10,7 +10,8 @@ into the next group's pass) on the GPU, through the C ABI:
   pairs exceed what one pass indexes (2^31), built in two groups: nnz against the
   closed form, sampled rows against the oracle, zero row sums of the whole matrix;
 * the groups streamed from pinned host memory (kb_build_lower_csr_group_pass), equal to
-  the device-resident grouped build bit for bit.
+  the device-resident grouped build bit for bit;
+* the pass-3 table size set by hand, bit for bit the built-in one.
 """
 from __future__ import annotations
 
@@ -173,3 +174,23 @@ def test_streamed_groups_from_host_memory(prec):
     assert scaled_error(orp, ocol, val.astype(np.float64), oval) <= TOL[prec]
     with pytest.raises(ValueError):  # device tensors are refused: the path reads host memory
         sb.run(dev[0], dev[1], dev[2])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32fb64"])
+@pytest.mark.parametrize("slots", [512, 4096])
+def test_grouped_table_slots(slots, prec):
+    """The pass-3 table size set by hand in a grouped build (the passes that also write
+    residuals, whose FP64 variant keeps a column array of its own: its largest table at
+    4096 slots): bit for bit the grouped build with the built-in table size.  With 512
+    slots and 32-row sub-buckets the randomly numbered tets' last sub-buckets overflow to
+    the heavy path."""
+    m = meshgen.config_mesh(3, n=14)
+    dev = to_dev(m)
+    cap = box_nnz(4, 14, 14, 14)
+    ref = kb.build_lower_csr_grouped(*dev, m.elem, 5000, cap=cap, prec=prec)
+    got = kb.build_lower_csr_grouped(*dev, m.elem, 5000, cap=cap, prec=prec,
+                                     tuning=kb.Tuning(sub_bits=5, table_slots=slots))
+    say(f"[grouped-slots] slots={slots} {prec} nnz={got.nnz}")
+    assert got.nnz == ref.nnz
+    for x, y in zip(np_csr(got), np_csr(ref)):
+        assert np.array_equal(x.view(np.uint8), y.view(np.uint8))
