@@ -89,6 +89,17 @@ def source_digest() -> str:
     return h.hexdigest()
 
 
+def pass1_kernel(elem: int, prec: str, op: str) -> str:
+    """The pass-1 kernel a build from coordinates launches: tets in the persistent tet
+    kernel; bricks in FP64 two tiles per workgroup, in FP32 a lane pair per element for the
+    stiffness matrix, else one lane per element."""
+    if elem == 4:
+        return "k_pass1_tet"
+    if prec == "fp64":
+        return "k_pass1_two"
+    return "k_pass1_pair" if op == "stiffness" else "k_pass1"
+
+
 def stored_traffic(kernel: str, workload: str, prec: str):
     """HBM bytes per launch of `kernel` from the committed counter summary, if it was
     taken on the current sources (else None).  The summary holds lines
@@ -527,9 +538,8 @@ def main():
     elif stages:
         dom = max(SINGLE_KERNEL_STAGES, key=lambda k: stages[k])
         kernel = SINGLE_KERNEL_STAGES[dom]
-        if dom == "integrate":  # the pass-1 variant the build launches
-            kernel = "k_pass1_tet" if m.elem == 4 else ("k_pass1_two" if prec == "fp64" else
-                                                        "k_pass1_pair" if args.op == "stiffness" else "k_pass1")
+        if dom == "integrate":
+            kernel = pass1_kernel(m.elem, prec, args.op)
         achieved = ab[dom] / (stages[dom] * 1e-3) / 1e9
         traffic = stored_traffic(kernel, args.workload, prec)
         out["roofline"] = {"bound": "hbm", "kernel": kernel, "stage": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,

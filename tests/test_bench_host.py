@@ -52,3 +52,15 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU only" in r.stderr
+
+
+def test_pass1_kernel_names_the_launched_variant():
+    """The roofline's pass-1 kernel is the one the launch code picks (and a name that
+    occurs in the kernel sources)."""
+    src = open(os.path.join(os.path.dirname(bench.__file__), "paper_1501_04784_amd", "csrc", "kb_assemble.hpp")).read()
+    cases = {(4, "fp32fb64", "stiffness"): "k_pass1_tet", (4, "fp64", "mass"): "k_pass1_tet",
+             (8, "fp64", "stiffness"): "k_pass1_two", (8, "fp64", "mass"): "k_pass1_two",
+             (8, "fp32fb64", "stiffness"): "k_pass1_pair", (8, "fp32", "mass"): "k_pass1"}
+    for (elem, prec, op), name in cases.items():
+        assert bench.pass1_kernel(elem, prec, op) == name
+        assert f"void {name}(" in src
