@@ -58,7 +58,7 @@ struct Plan {
   size_t lds1 = 0, lds2 = 0;
   // workspace offsets
   size_t o_coords4 = 0, o_hist = 0, o_csum = 0, o_tot = 0, o_part = 0, o_total = 0, o_bstart = 0, o_segbase = 0, o_hist2 = 0, o_seg2b = 0, o_emax = 0,
-         o_dconn = 0, o_ovl = 0, o_tres = 0, o_row1 = 0, o_col1 = 0, o_val1 = 0, o_key2 = 0, o_val2 = 0, o_sbb = 0, o_rowoff = 0, o_usub = 0, o_ubase = 0,
+         o_dconn = 0, o_ovl = 0, o_hvy = 0, o_tres = 0, o_row1 = 0, o_col1 = 0, o_val1 = 0, o_key2 = 0, o_val2 = 0, o_sbb = 0, o_rowoff = 0, o_usub = 0, o_ubase = 0,
          total = 0;
 };
 
@@ -251,6 +251,7 @@ int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p, int dof 
   p->o_seg2b = take(4 * (size_t)p->nseg_max);
   p->o_emax = take(8);  // largest value exponent, then the count of heavy sub-buckets
   p->o_ovl = take(4 * (size_t)p->nsub);  // heavy sub-buckets (k_pass3_heavy)
+  p->o_hvy = take(4 * (size_t)kHeavyPar * kHvyWords);  // their first-level ranges (k_pass3_heavy_ranges)
   p->o_dconn = take(p->dof > 1 ? 4 * (size_t)p->nen * (size_t)p->nel : 0);  // expanded connectivity
   p->o_tres = take(csr_cap > 0 ? p->vbytes * T : 0);  // residuals of the reduced entries
   p->o_row1 = take(2 * T);
@@ -419,7 +420,7 @@ struct Carry {
 // workgroups return at once when there are none)
 template <typename V, bool RES>
 int launch_pass3(const Plan& p, uint32_t* key2, V* val2, uint32_t* sbb, uint32_t* emax, int32_t* tcol, V* tval,
-                 V* tres, uint32_t* rowoff, uint32_t* usub, uint32_t* ov_list, hipStream_t s) {
+                 V* tres, uint32_t* rowoff, uint32_t* usub, uint32_t* ov_list, uint32_t* hvy, hipStream_t s) {
   const unsigned g3 = (unsigned)p.nsub;
   uint32_t* ov_count = emax + 1;
   switch (p.ht) {
@@ -445,7 +446,17 @@ int launch_pass3(const Plan& p, uint32_t* key2, V* val2, uint32_t* sbb, uint32_t
   if (!set_lds(kh, HeavySmem::bytes())) return KB_EHIP;
   const unsigned gh = (unsigned)std::min<int64_t>(p.nsub, kHeavyGrid);
   kh<<<gh, kHeavyThreads, HeavySmem::bytes(), s>>>(key2, val2, (uint32_t*)tcol, tval, sbb, p.s2, p.colbits, p.nn, emax,
-                                                   tres, rowoff, usub, ov_list, ov_count);
+                                                   tres, rowoff, usub, ov_list, ov_count, hvy);
+  KB_LAUNCH_CHECK();
+  // the first-level ranges of up to kHeavyPar of them, by one workgroup per compute unit,
+  // then their entries moved together (both return at once when there are none)
+  auto kr = k_pass3_heavy_ranges<V, RES>;
+  if (!set_lds(kr, HeavySmem::bytes())) return KB_EHIP;
+  kr<<<(unsigned)std::max(1, p.cus), kHeavyThreads, HeavySmem::bytes(), s>>>(key2, val2, (uint32_t*)tcol, tval,
+                                                                           p.colbits, emax, tres, ov_count, hvy);
+  KB_LAUNCH_CHECK();
+  k_pass3_heavy_finish<V, RES><<<(unsigned)kHeavyPar, kFinishThreads, 0, s>>>((uint32_t*)tcol, tval, tres, sbb, p.s2,
+                                                                            p.nn, rowoff, usub, ov_list, ov_count, hvy);
   KB_LAUNCH_CHECK();
   return KB_OK;
 }
@@ -497,10 +508,11 @@ int assemble_tail(const Plan& p, unsigned char* ws, int32_t* row_ptr, int32_t* c
   KB_TRY(ev.rec(KB_STAGE_REDUCE));
   if (p.nsub > 0) {
     auto* ov_list = (uint32_t*)(ws + p.o_ovl);
+    auto* hvy = (uint32_t*)(ws + p.o_hvy);
     if (cr)
-      KB_TRY((launch_pass3<V, true>(p, key2, val2, sbb, emax, tcol, tval, tres, rowoff, usub, ov_list, s)));
+      KB_TRY((launch_pass3<V, true>(p, key2, val2, sbb, emax, tcol, tval, tres, rowoff, usub, ov_list, hvy, s)));
     else
-      KB_TRY((launch_pass3<V, false>(p, key2, val2, sbb, emax, tcol, tval, nullptr, rowoff, usub, ov_list, s)));
+      KB_TRY((launch_pass3<V, false>(p, key2, val2, sbb, emax, tcol, tval, nullptr, rowoff, usub, ov_list, hvy, s)));
   }
   KB_TRY(ev.rec(KB_STAGE_COMPRESS));
   KB_TRY(scan((const int32_t*)usub, p.nsub, part, (int32_t*)ubase, nnz_dev, s));

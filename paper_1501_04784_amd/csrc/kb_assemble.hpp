@@ -1484,6 +1484,48 @@ __device__ __forceinline__ int heavy_shift(uint32_t w) {
   return bits - 11 > 12 ? bits - 11 : 12;  // at most kDigits digits
 }
 
+// One first-level digit range [a, b) of a heavy sub-bucket, in (akey, aval), keys in
+// [k0, k0 + w): a leaf, or split again into (ikey, ival) at the same place and its leaves
+// summed in key order.  Entries written from tcol / tval / tres [u0 ...); returns their
+// number.  The range's pairs are all read before any entry is written, and a range has
+// at most as many entries as pairs.
+template <typename V, bool RES>
+__device__ uint32_t heavy_range(const HeavySmem& sm, uint32_t* ikey, V* ival, uint32_t* akey, V* aval, uint32_t a,
+                                uint32_t b, uint32_t k0, uint32_t w, int F, int colbits, int32_t* tcol, V* tval,
+                                V* tres, uint32_t u0) {
+  const int sh1 = heavy_shift(w);
+  if (sh1 == 0) return heavy_leaf<V, RES>(sm, akey, aval, a, b, k0, F, colbits, tcol, tval, tres, u0);
+  const int nd1 = (int)((w - 1) >> sh1) + 1;
+  uint32_t* st1 = sm.start + (kDigits + 1);
+  heavy_split<V>(sm, akey, aval, ikey, ival, a, b, k0, sh1, nd1, st1);
+  uint32_t U = 0;
+  for (int d1 = 0; d1 < nd1; ++d1) {  // leaves (sh1 = 12 after a first split)
+    const uint32_t a1 = st1[d1], b1 = st1[d1 + 1];
+    if (a1 == b1) continue;
+    U += heavy_leaf<V, RES>(sm, ikey, ival, a1, b1, k0 + ((uint32_t)d1 << sh1), F, colbits, tcol, tval, tres, u0 + U);
+  }
+  return U;
+}
+
+// The first kHeavyPar heavy sub-buckets that need a split have their first-level digit
+// ranges reduced by many workgroups (k_pass3_heavy_ranges) and are then finished by
+// k_pass3_heavy_finish; the table holds, per such sub-bucket, the digit starts, the
+// entries of each range, the entries per row, and (key base, shift, digits, key width)
+constexpr int kHeavyPar = 64;
+constexpr int kHvyWords = (kDigits + 1) + kDigits + 256 + 4;
+struct HeavyTable {
+  uint32_t* st;    // [kDigits + 1] digit starts (absolute pair positions)
+  uint32_t* ucnt;  // [kDigits] entries of each digit range
+  uint32_t* rcnt;  // [256] entries of each row of the sub-bucket
+  uint32_t* meta;  // [4] kmin, shift, digits (0: finished by k_pass3_heavy), key width
+  __device__ HeavyTable(uint32_t* hvy, uint32_t it) {
+    st = hvy + (size_t)it * kHvyWords;
+    ucnt = st + kDigits + 1;
+    rcnt = ucnt + kDigits;
+    meta = rcnt + 256;
+  }
+};
+
 // (the pair buffers alias the output, so they carry no __restrict__)
 template <typename V, bool RES = false>
 __global__ __launch_bounds__(kHeavyThreads) void k_pass3_heavy(uint32_t* ikey, V* ival, uint32_t* akey, V* aval,
@@ -1492,7 +1534,8 @@ __global__ __launch_bounds__(kHeavyThreads) void k_pass3_heavy(uint32_t* ikey, V
                                                              V* __restrict__ tres, uint32_t* __restrict__ rowoff,
                                                              uint32_t* __restrict__ usub,
                                                              const uint32_t* __restrict__ ov_list,
-                                                             const uint32_t* __restrict__ ov_count) {
+                                                             const uint32_t* __restrict__ ov_count,
+                                                             uint32_t* __restrict__ hvy) {
   extern __shared__ __align__(16) unsigned char smem[];
   const HeavySmem sm(smem);
   const uint32_t n_over = *ov_count;
@@ -1529,30 +1572,33 @@ __global__ __launch_bounds__(kHeavyThreads) void k_pass3_heavy(uint32_t* ikey, V
     if (sh0 == 0) {
       U = heavy_leaf<V, RES>(sm, ikey, ival, beg, end, kmin, F, colbits, tcol + beg, aval + beg,
                              RES ? tres + beg : nullptr, 0);
+      if (it < (uint32_t)kHeavyPar && threadIdx.x == 0) HeavyTable(hvy, it).meta[2] = 0u;  // finished here
     } else {
       const int nd0 = (int)((w0 - 1) >> sh0) + 1;
       uint32_t* st0 = sm.start;
       heavy_split<V>(sm, ikey, ival, akey, aval, beg, end, kmin, sh0, nd0, st0);
+      if (it < (uint32_t)kHeavyPar) {
+        // the digit ranges go to k_pass3_heavy_ranges, the rest to k_pass3_heavy_finish
+        const HeavyTable t(hvy, it);
+        for (int d = threadIdx.x; d <= nd0; d += kHeavyThreads) t.st[d] = st0[d];
+        for (int d = threadIdx.x; d < nd0; d += kHeavyThreads) t.ucnt[d] = 0u;
+        for (int r = threadIdx.x; r < 256; r += kHeavyThreads) t.rcnt[r] = 0u;
+        if (threadIdx.x == 0) {
+          t.meta[0] = kmin;
+          t.meta[1] = (uint32_t)sh0;
+          t.meta[2] = (uint32_t)nd0;
+          t.meta[3] = w0;
+        }
+        heavy_sync();
+        continue;
+      }
       for (int d0 = 0; d0 < nd0; ++d0) {
         const uint32_t a = st0[d0], b = st0[d0 + 1];
         if (a == b) continue;
         const uint32_t k0 = kmin + ((uint32_t)d0 << sh0);
         const uint32_t w1 = (1u << sh0) < (kmin + w0 - k0) ? (1u << sh0) : (kmin + w0 - k0);
-        const int sh1 = heavy_shift(w1);
-        if (sh1 == 0) {  // a leaf, in the alternate buffer
-          U += heavy_leaf<V, RES>(sm, akey, aval, a, b, k0, F, colbits, tcol + beg, aval + beg,
-                                  RES ? tres + beg : nullptr, U);
-          continue;
-        }
-        const int nd1 = (int)((w1 - 1) >> sh1) + 1;
-        uint32_t* st1 = sm.start + (kDigits + 1);
-        heavy_split<V>(sm, akey, aval, ikey, ival, a, b, k0, sh1, nd1, st1);
-        for (int d1 = 0; d1 < nd1; ++d1) {  // leaves (sh1 = 12 after a first split)
-          const uint32_t a1 = st1[d1], b1 = st1[d1 + 1];
-          if (a1 == b1) continue;
-          U += heavy_leaf<V, RES>(sm, ikey, ival, a1, b1, k0 + ((uint32_t)d1 << sh1), F, colbits, tcol + beg,
-                                  aval + beg, RES ? tres + beg : nullptr, U);
-        }
+        U += heavy_range<V, RES>(sm, ikey, ival, akey, aval, a, b, k0, w1, F, colbits, tcol + beg, aval + beg,
+                                 RES ? tres + beg : nullptr, U);
       }
     }
     // row offsets within the sub-bucket
@@ -1582,6 +1628,140 @@ __global__ __launch_bounds__(kHeavyThreads) void k_pass3_heavy(uint32_t* ikey, V
     if (threadIdx.x == 0) usub[g] = U;
     heavy_sync();
   }
+}
+
+// The first-level digit ranges of the heavy sub-buckets that k_pass3_heavy split and
+// recorded (the first kHeavyPar of the list): range d0 of sub-bucket it is reduced by
+// workgroup d0 mod gridDim.x, its entries written from its own first pair's place (its
+// pairs all read before; other workgroups read other ranges), its entry count and its
+// entries per row recorded in the table.
+template <typename V, bool RES = false>
+__global__ __launch_bounds__(kHeavyThreads) void k_pass3_heavy_ranges(uint32_t* ikey, V* ival, uint32_t* akey,
+                                                                    V* aval, int colbits,
+                                                                    const uint32_t* __restrict__ emax,
+                                                                    V* __restrict__ tres,
+                                                                    const uint32_t* __restrict__ ov_count,
+                                                                    uint32_t* __restrict__ hvy) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const HeavySmem sm(smem);
+  const uint32_t n_over = *ov_count;
+  const uint32_t npar = n_over < (uint32_t)kHeavyPar ? n_over : (uint32_t)kHeavyPar;
+  if (npar == 0) return;
+  for (int h = threadIdx.x; h < kLeafKeys; h += kHeavyThreads) {
+    sm.lo[h] = 0ull;
+    sm.hi[h] = 0ll;
+    sm.top[h] = 0ll;
+  }
+  if (threadIdx.x < kLeafKeys / 4) ((uint32_t*)sm.occ)[threadIdx.x] = 0u;
+  for (int r = threadIdx.x; r < 256; r += kHeavyThreads) sm.rowcnt[r] = 0u;
+  __syncthreads();
+  const int F = 1117 - (int)*emax;
+  int32_t* const tcol = (int32_t*)akey;
+  for (uint32_t it = 0; it < npar; ++it) {
+    const HeavyTable t(hvy, it);
+    const uint32_t nd0 = t.meta[2];
+    if (nd0 == 0) continue;  // reduced whole by k_pass3_heavy
+    const uint32_t kmin = t.meta[0], sh0 = t.meta[1], w0 = t.meta[3];
+    for (uint32_t d0 = blockIdx.x; d0 < nd0; d0 += gridDim.x) {
+      const uint32_t a = t.st[d0], b = t.st[d0 + 1];
+      if (a == b) continue;
+      const uint32_t k0 = kmin + (d0 << sh0);
+      const uint32_t w1 = (1u << sh0) < (kmin + w0 - k0) ? (1u << sh0) : (kmin + w0 - k0);
+      const uint32_t U = heavy_range<V, RES>(sm, ikey, ival, akey, aval, a, b, k0, w1, F, colbits, tcol + a,
+                                             aval + a, RES ? tres + a : nullptr, 0);
+      if (threadIdx.x == 0) t.ucnt[d0] = U;
+      for (int r = threadIdx.x; r < 256; r += kHeavyThreads) {
+        const uint32_t c = sm.rowcnt[r];
+        if (c) {
+          atomicAdd(&t.rcnt[r], c);
+          sm.rowcnt[r] = 0u;
+        }
+      }
+      heavy_sync();
+    }
+  }
+}
+
+// One workgroup per sub-bucket of the table: the ranges' entries moved together, in
+// range order, to the sub-bucket's first pair's place (as k_pass3_heavy leaves them), the
+// row offsets within the sub-bucket and its entry count.  A range's entries move down
+// (never past the next range's first pair): each chunk is read, parked in LDS, and only
+// then written.
+constexpr int kFinishThreads = 1024;
+template <typename V, bool RES = false>
+__global__ __launch_bounds__(kFinishThreads) void k_pass3_heavy_finish(uint32_t* akey, V* aval, V* tres,
+                                                                     const uint32_t* __restrict__ sbb, int s2,
+                                                                     int64_t n_node, uint32_t* __restrict__ rowoff,
+                                                                     uint32_t* __restrict__ usub,
+                                                                     const uint32_t* __restrict__ ov_list,
+                                                                     const uint32_t* __restrict__ ov_count,
+                                                                     const uint32_t* __restrict__ hvy) {
+  __shared__ uint32_t s_off[kDigits + 1];
+  __shared__ uint32_t s_scan[kFinishThreads / 64 + 1];
+  __shared__ int32_t s_col[kFinishThreads];
+  __shared__ V s_val[kFinishThreads];
+  __shared__ V s_res[RES ? kFinishThreads : 1];
+  const uint32_t n_over = *ov_count;
+  const uint32_t it = blockIdx.x;
+  if (it >= n_over || it >= (uint32_t)kHeavyPar) return;
+  const HeavyTable t(const_cast<uint32_t*>(hvy), it);
+  const uint32_t nd0 = t.meta[2];
+  if (nd0 == 0) return;
+  const int64_t g = ov_list[it];
+  const uint32_t beg = sbb[g];
+  for (uint32_t d = threadIdx.x; d < nd0; d += kFinishThreads) s_off[d] = t.ucnt[d];
+  __syncthreads();
+  const uint32_t U = block_scan_array(s_off, (int)nd0, s_scan);  // (ends with a barrier)
+  if (threadIdx.x == 0) s_off[nd0] = U;
+  __syncthreads();
+  int32_t* const tcol = (int32_t*)akey;
+  for (uint32_t d = 0; d < nd0; ++d) {
+    const uint32_t n = s_off[d + 1] - s_off[d];
+    const uint32_t src = t.st[d], dst = beg + s_off[d];
+    if (n == 0 || src == dst) continue;
+    for (uint32_t c = 0; c < n; c += kFinishThreads) {
+      const uint32_t f = c + threadIdx.x;
+      if (f < n) {
+        s_col[threadIdx.x] = tcol[src + f];
+        s_val[threadIdx.x] = aval[src + f];
+        if constexpr (RES) s_res[threadIdx.x] = tres[src + f];
+      }
+      __syncthreads();
+      if (f < n) {
+        tcol[dst + f] = s_col[threadIdx.x];
+        aval[dst + f] = s_val[threadIdx.x];
+        if constexpr (RES) tres[dst + f] = s_res[threadIdx.x];
+      }
+      __syncthreads();
+    }
+  }
+  // row offsets within the sub-bucket from the entries per row
+  const int64_t r0 = g << s2;
+  const int R = (int)min((int64_t)1 << s2, n_node - r0);
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    uint32_t v[4], sum = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int r = lane * 4 + k;
+      v[k] = r < R ? t.rcnt[r] : 0u;
+      sum += v[k];
+    }
+    uint32_t x = sum;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t y = __shfl_up(x, d, 64);
+      if (lane >= d) x += y;
+    }
+    uint32_t run = x - sum;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int r = lane * 4 + k;
+      if (r < R) rowoff[r0 + r] = run;
+      run += v[k];
+    }
+  }
+  if (threadIdx.x == 0) usub[g] = U;
 }
 
 // ------------------------------------------------------------------------- final
