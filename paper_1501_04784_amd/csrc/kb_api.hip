@@ -32,6 +32,7 @@ constexpr int kTargetBuckets = 256;  // first-level buckets (pass-1 run length)
 constexpr double kSubEntries = 300;   // target distinct entries per sub-bucket
 constexpr int kHTMin = 512, kHTMax = 4096;
 constexpr int kHeavyGrid = 64;  // workgroups of k_pass3_heavy (each takes whole sub-buckets)
+static_assert(kHeavyGrid >= kHeavyPar, "k_pass3_heavy's first kHeavyPar workgroups clear the split tables");
 constexpr unsigned kFinalHeavyGrid = 256;  // workgroups copying the entries of heavy sub-buckets
 constexpr double kHalfTileRatio = 16;   // pairs per tile x bucket histogram entry
 constexpr size_t kWideStage = 112640;  // staged pair bytes per pass-1 tile, elements of > 8 rows
@@ -448,8 +449,21 @@ int launch_pass3(const Plan& p, uint32_t* key2, V* val2, uint32_t* sbb, uint32_t
   kh<<<gh, kHeavyThreads, HeavySmem::bytes(), s>>>(key2, val2, (uint32_t*)tcol, tval, sbb, p.s2, p.colbits, p.nn, emax,
                                                    tres, rowoff, usub, ov_list, ov_count, hvy);
   KB_LAUNCH_CHECK();
-  // the first-level ranges of up to kHeavyPar of them, by one workgroup per compute unit,
-  // then their entries moved together (both return at once when there are none)
+  // up to kHeavyPar of them split by many workgroups, their first-level ranges reduced
+  // by one workgroup per compute unit, then their entries moved together (all return at
+  // once when there are none)
+  const unsigned gsplit = (unsigned)std::max(1, 2 * p.cus);
+  k_heavy_rows<<<gsplit, kHeavyThreads, 0, s>>>(key2, sbb, p.colbits, ov_list, ov_count, hvy);
+  KB_LAUNCH_CHECK();
+  k_heavy_layout<<<(unsigned)kHeavyPar, kHvyRows, 0, s>>>(sbb, p.colbits, ov_list, ov_count, hvy);
+  KB_LAUNCH_CHECK();
+  k_heavy_hist<<<gsplit, kHeavyThreads, 0, s>>>(key2, sbb, p.colbits, ov_list, ov_count, hvy);
+  KB_LAUNCH_CHECK();
+  k_heavy_starts<<<(unsigned)kHeavyPar, kHeavyThreads, 0, s>>>(sbb, ov_list, ov_count, hvy);
+  KB_LAUNCH_CHECK();
+  k_heavy_scatter<V><<<gsplit, kHeavyThreads, 0, s>>>(key2, val2, (uint32_t*)tcol, tval, sbb, p.colbits, ov_list,
+                                                      ov_count, hvy);
+  KB_LAUNCH_CHECK();
   auto kr = k_pass3_heavy_ranges<V, RES>;
   if (!set_lds(kr, HeavySmem::bytes())) return KB_EHIP;
   kr<<<(unsigned)std::max(1, p.cus), kHeavyThreads, HeavySmem::bytes(), s>>>(key2, val2, (uint32_t*)tcol, tval,
@@ -519,20 +533,21 @@ int assemble_tail(const Plan& p, unsigned char* ws, int32_t* row_ptr, int32_t* c
   if (p.nsub > 0) {
     const unsigned gf = (unsigned)div_up(p.nsub, 4);
     auto* ov_list = (const uint32_t*)(ws + p.o_ovl);
+    auto* hvy = (const uint32_t*)(ws + p.o_hvy);
     const uint32_t* ov_count = emax + 1;
     if (cr) {
       k_final<V, true><<<gf, 256, 0, s>>>(sbb, ubase, tcol, tval, tres, rowoff, p.s2, p.nn, p.nsub, row_ptr, col_idx,
                                           vals, (V*)cr->res_out, cr->rows_out, cap, status);
       KB_LAUNCH_CHECK();
       k_final_heavy<V, true><<<kFinalHeavyGrid, 256, 0, s>>>(sbb, ubase, tcol, tval, tres, rowoff, p.s2, p.nn, p.nsub,
-                                                            ov_list, ov_count, col_idx, vals, (V*)cr->res_out,
+                                                            ov_list, ov_count, hvy, col_idx, vals, (V*)cr->res_out,
                                                             cr->rows_out, cap);
     } else {
       k_final<V><<<gf, 256, 0, s>>>(sbb, ubase, tcol, tval, nullptr, rowoff, p.s2, p.nn, p.nsub, row_ptr, col_idx,
                                     vals, nullptr, nullptr, cap, status);
       KB_LAUNCH_CHECK();
       k_final_heavy<V><<<kFinalHeavyGrid, 256, 0, s>>>(sbb, ubase, tcol, tval, nullptr, rowoff, p.s2, p.nn, p.nsub,
-                                                      ov_list, ov_count, col_idx, vals, nullptr, nullptr, cap);
+                                                      ov_list, ov_count, hvy, col_idx, vals, nullptr, nullptr, cap);
     }
     KB_LAUNCH_CHECK();
   } else {

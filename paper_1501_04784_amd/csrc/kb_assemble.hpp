@@ -1052,6 +1052,60 @@ __global__ __launch_bounds__(NT) void k_scatter2(const uint16_t* __restrict__ ir
   }
 }
 
+// The first kHeavyPar heavy sub-buckets of the list are split, and their first-level
+// digit ranges reduced, by many workgroups (k_heavy_rows, k_heavy_layout, k_heavy_hist,
+// k_heavy_starts, k_heavy_scatter, k_pass3_heavy_ranges); k_pass3_heavy_finish then
+// sums up each one's entries and k_final_heavy gathers them from the ranges.
+// k_pass3_heavy clears their tables and takes the other listed sub-buckets whole.
+// The first-level digits follow the rows: row r of a sub-bucket gets n_r digits (a
+// power of two, none for a row without pairs), each covering 2^(colbits) / n_r columns,
+// with n_r about kHvyShare times the row's share of the pairs, at most one digit per
+// leaf width of columns, and at least 2^(colbits - 23) so that a digit is at most 2^23
+// keys wide (split once more into leaves).  A row holding most pairs of its sub-bucket
+// is thus cut into leaf-wide digits that many workgroups reduce side by side.  The
+// digits of all rows total at most kHvyShare + 256 + 256 = kHvyDigits.
+constexpr int kHeavyPar = 64;
+constexpr int kHvyDigits = 2048;  // first-level digits at most (= kDigits of the heavy section)
+constexpr uint32_t kHvyShare = 1536;
+constexpr int kHvyRows = 256;  // rows of a sub-bucket at most
+constexpr int kHvyWords = (kHvyDigits + 1) + 2 * kHvyDigits + 3 * kHvyRows + (kHvyRows + 1) + 4;
+struct HeavyTable {
+  uint32_t* st;     // [kHvyDigits + 1] digit starts (absolute pair positions)
+  uint32_t* ucnt;   // [kHvyDigits] entries of each digit range, then their offsets
+  uint32_t* hist;   // [kHvyDigits] pairs of each digit, then the scatter's cursors
+  uint32_t* rcnt;   // [kHvyRows] entries of each row
+  uint32_t* rpair;  // [kHvyRows] pairs of each row
+  uint32_t* rsh;    // [kHvyRows] column shift of each row's digits
+  uint32_t* rbase;  // [kHvyRows + 1] first digit of each row; rbase[kHvyRows] = digits
+  uint32_t* meta;   // [4] digits
+  __device__ HeavyTable(uint32_t* hvy, uint32_t it) {
+    st = hvy + (size_t)it * kHvyWords;
+    ucnt = st + kHvyDigits + 1;
+    hist = ucnt + kHvyDigits;
+    rcnt = hist + kHvyDigits;
+    rpair = rcnt + kHvyRows;
+    rsh = rpair + kHvyRows;
+    rbase = rsh + kHvyRows;
+    meta = rbase + kHvyRows + 1;
+  }
+};
+
+// table entry it of a listed sub-bucket: the row counts cleared
+__device__ __forceinline__ void heavy_table_init(uint32_t* hvy, uint32_t it) {
+  const HeavyTable t(hvy, it);
+  for (uint32_t r = threadIdx.x; r < (uint32_t)kHvyRows; r += blockDim.x) {
+    t.rcnt[r] = 0u;
+    t.rpair[r] = 0u;
+  }
+}
+
+// first-level digit of key k (row k >> colbits) from the layout in LDS
+__device__ __forceinline__ uint32_t heavy_digit(uint32_t k, int colbits, const uint32_t* s_rbase,
+                                                const uint32_t* s_rsh) {
+  const uint32_t r = k >> colbits;
+  return s_rbase[r] + ((k & ((1u << colbits) - 1u)) >> s_rsh[r]);
+}
+
 // ------------------------------------------------------------------------ pass 3
 // home slot of a packed key in a table of HT (a power of two) slots: the top bits of
 // the key mixed by xor-shift, multiply by 2^32/phi, xor-shift.  A plain multiplicative
@@ -1404,8 +1458,30 @@ __device__ uint32_t heavy_leaf(const HeavySmem& sm, const uint32_t* key, const V
   // unsigned, below 2^47 in magnitude signed) stay inside 64 bits
   constexpr uint32_t kRound = 65532;
   const int lane = threadIdx.x & 63;
+  // the wave's kept slot: once a slot has been hot (held by more than one lane), the
+  // lanes that meet it again while it is the wave's first lane's slot add its chunks to
+  // their own sums, which are summed over the wave and added once, at the end of the
+  // round (a key that owns most of the leaf, such as a heavy node's diagonal, then costs
+  // two register additions per pair)
   for (uint32_t r = a; r < b; r += kRound) {
     const uint32_t re = b - r > kRound ? r + kRound : b;
+    uint32_t kept = kEmptyKey;  // (uniform)
+    unsigned long long k0 = 0ull;
+    long long k1 = 0ll;
+    const auto flush = [&]() {  // the kept sums over the wave, added to the kept slot
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) {
+        k0 += __shfl_xor(k0, o, 64);
+        k1 += __shfl_xor(k1, o, 64);
+      }
+      if (lane == 0) {
+        atomicAdd(&sm.lo[kept], k0);
+        atomicAdd((unsigned long long*)&sm.hi[kept], (unsigned long long)k1);
+        sm.occ[kept] = 1;
+      }
+      k0 = 0ull;
+      k1 = 0ll;
+    };
     heavy_stream<true>(key, val, r, re, [&](uint32_t k, V v, bool ok) {
       const uint32_t h = k - kmin;
       uint64_t c0;
@@ -1413,26 +1489,24 @@ __device__ uint32_t heavy_leaf(const HeavySmem& sm, const uint32_t* key, const V
       to_chunks(v, F, c0, c1);
       uint32_t hot;
       const uint64_t m = heavy_hot(h, ok, hot);
-      if (ok && !((m >> lane) & 1ull)) {
+      const bool mine = (m >> lane) & 1ull;
+      if (ok && !mine) {
         atomicAdd(&sm.lo[h], (unsigned long long)c0);
         atomicAdd((unsigned long long*)&sm.hi[h], (unsigned long long)c1);
         sm.occ[h] = 1;
       }
-      if (m) {  // the hot lanes' chunks summed over the wave (64 chunks stay below 2^54)
-        unsigned long long s0 = ((m >> lane) & 1ull) ? c0 : 0ull;
-        long long s1 = ((m >> lane) & 1ull) ? c1 : 0ll;
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) {
-          s0 += __shfl_xor(s0, o, 64);
-          s1 += __shfl_xor(s1, o, 64);
+      if (m) {
+        if (hot != kept) {  // (uniform) a new kept slot: the old one's sums go first
+          if (kept != kEmptyKey) flush();
+          kept = hot;
         }
-        if (lane == 0) {
-          atomicAdd(&sm.lo[hot], s0);
-          atomicAdd((unsigned long long*)&sm.hi[hot], (unsigned long long)s1);
-          sm.occ[hot] = 1;
+        if (mine) {  // (64 lanes x 64 pairs of a round: the sums stay below 2^60)
+          k0 += c0;
+          k1 += c1;
         }
       }
     });
+    if (kept != kEmptyKey) flush();
     __syncthreads();
     heavy_normalise(sm);
     __syncthreads();
@@ -1507,25 +1581,6 @@ __device__ uint32_t heavy_range(const HeavySmem& sm, uint32_t* ikey, V* ival, ui
   return U;
 }
 
-// The first kHeavyPar heavy sub-buckets that need a split have their first-level digit
-// ranges reduced by many workgroups (k_pass3_heavy_ranges) and are then finished by
-// k_pass3_heavy_finish; the table holds, per such sub-bucket, the digit starts, the
-// entries of each range, the entries per row, and (key base, shift, digits, key width)
-constexpr int kHeavyPar = 64;
-constexpr int kHvyWords = (kDigits + 1) + kDigits + 256 + 4;
-struct HeavyTable {
-  uint32_t* st;    // [kDigits + 1] digit starts (absolute pair positions)
-  uint32_t* ucnt;  // [kDigits] entries of each digit range
-  uint32_t* rcnt;  // [256] entries of each row of the sub-bucket
-  uint32_t* meta;  // [4] kmin, shift, digits (0: finished by k_pass3_heavy), key width
-  __device__ HeavyTable(uint32_t* hvy, uint32_t it) {
-    st = hvy + (size_t)it * kHvyWords;
-    ucnt = st + kDigits + 1;
-    rcnt = ucnt + kDigits;
-    meta = rcnt + 256;
-  }
-};
-
 // (the pair buffers alias the output, so they carry no __restrict__)
 template <typename V, bool RES = false>
 __global__ __launch_bounds__(kHeavyThreads) void k_pass3_heavy(uint32_t* ikey, V* ival, uint32_t* akey, V* aval,
@@ -1539,7 +1594,9 @@ __global__ __launch_bounds__(kHeavyThreads) void k_pass3_heavy(uint32_t* ikey, V
   extern __shared__ __align__(16) unsigned char smem[];
   const HeavySmem sm(smem);
   const uint32_t n_over = *ov_count;
-  if (blockIdx.x >= n_over) return;
+  // (launched with at least kHeavyPar workgroups)
+  if (blockIdx.x < n_over && blockIdx.x < (uint32_t)kHeavyPar) heavy_table_init(hvy, blockIdx.x);
+  if ((uint32_t)kHeavyPar + blockIdx.x >= n_over) return;
   for (int h = threadIdx.x; h < kLeafKeys; h += kHeavyThreads) {
     sm.lo[h] = 0ull;
     sm.hi[h] = 0ll;
@@ -1548,7 +1605,7 @@ __global__ __launch_bounds__(kHeavyThreads) void k_pass3_heavy(uint32_t* ikey, V
   if (threadIdx.x < kLeafKeys / 4) ((uint32_t*)sm.occ)[threadIdx.x] = 0u;
   const int F = 1117 - (int)*emax;
   int32_t* const tcol = (int32_t*)akey;
-  for (uint32_t it = blockIdx.x; it < n_over; it += gridDim.x) {
+  for (uint32_t it = (uint32_t)kHeavyPar + blockIdx.x; it < n_over; it += gridDim.x) {
     const int64_t g = ov_list[it];
     const uint32_t beg = sbb[g], end = sbb[g + 1];
     const int64_t r0 = g << s2;
@@ -1556,7 +1613,7 @@ __global__ __launch_bounds__(kHeavyThreads) void k_pass3_heavy(uint32_t* ikey, V
     for (int r = threadIdx.x; r < 256; r += kHeavyThreads) sm.rowcnt[r] = 0u;
     // key range
     uint32_t mn = 0xFFFFFFFFu, mx = 0u;
-      heavy_stream<false>(ikey, ival, beg, end, [&](uint32_t k, V, bool ok) {
+    heavy_stream<false>(ikey, ival, beg, end, [&](uint32_t k, V, bool ok) {
       mn = ok && k < mn ? k : mn;
       mx = ok && k > mx ? k : mx;
     });
@@ -1572,26 +1629,10 @@ __global__ __launch_bounds__(kHeavyThreads) void k_pass3_heavy(uint32_t* ikey, V
     if (sh0 == 0) {
       U = heavy_leaf<V, RES>(sm, ikey, ival, beg, end, kmin, F, colbits, tcol + beg, aval + beg,
                              RES ? tres + beg : nullptr, 0);
-      if (it < (uint32_t)kHeavyPar && threadIdx.x == 0) HeavyTable(hvy, it).meta[2] = 0u;  // finished here
     } else {
       const int nd0 = (int)((w0 - 1) >> sh0) + 1;
       uint32_t* st0 = sm.start;
       heavy_split<V>(sm, ikey, ival, akey, aval, beg, end, kmin, sh0, nd0, st0);
-      if (it < (uint32_t)kHeavyPar) {
-        // the digit ranges go to k_pass3_heavy_ranges, the rest to k_pass3_heavy_finish
-        const HeavyTable t(hvy, it);
-        for (int d = threadIdx.x; d <= nd0; d += kHeavyThreads) t.st[d] = st0[d];
-        for (int d = threadIdx.x; d < nd0; d += kHeavyThreads) t.ucnt[d] = 0u;
-        for (int r = threadIdx.x; r < 256; r += kHeavyThreads) t.rcnt[r] = 0u;
-        if (threadIdx.x == 0) {
-          t.meta[0] = kmin;
-          t.meta[1] = (uint32_t)sh0;
-          t.meta[2] = (uint32_t)nd0;
-          t.meta[3] = w0;
-        }
-        heavy_sync();
-        continue;
-      }
       for (int d0 = 0; d0 < nd0; ++d0) {
         const uint32_t a = st0[d0], b = st0[d0 + 1];
         if (a == b) continue;
@@ -1630,11 +1671,256 @@ __global__ __launch_bounds__(kHeavyThreads) void k_pass3_heavy(uint32_t* ikey, V
   }
 }
 
-// The first-level digit ranges of the heavy sub-buckets that k_pass3_heavy split and
-// recorded (the first kHeavyPar of the list): range d0 of sub-bucket it is reduced by
-// workgroup d0 mod gridDim.x, its entries written from its own first pair's place (its
-// pairs all read before; other workgroups read other ranges), its entry count and its
-// entries per row recorded in the table.
+// ---- the split of the first kHeavyPar listed sub-buckets, by many workgroups.  Their
+// pairs are cut into chunks of kSplitChunk (a sub-bucket's last chunk shorter); each
+// workgroup takes chunks j = blockIdx.x, blockIdx.x + gridDim.x, ...  in list order.
+constexpr uint32_t kSplitChunk = 8192;
+
+// the listed sub-buckets' pair ranges and chunk prefix in LDS (npar <= kHeavyPar)
+__device__ __forceinline__ void heavy_chunk_table(const uint32_t* sbb, const uint32_t* ov_list, uint32_t npar,
+                                                  uint32_t* s_beg, uint32_t* s_end, uint32_t* s_c0) {
+  if (threadIdx.x < 64) {
+    const uint32_t it = threadIdx.x;
+    uint32_t a = 0, b = 0;
+    if (it < npar) {
+      const uint32_t g = ov_list[it];
+      a = sbb[g];
+      b = sbb[g + 1];
+    }
+    const uint32_t nc = (b - a + kSplitChunk - 1) / kSplitChunk;
+    uint32_t x = nc;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t y = __shfl_up(x, d, 64);
+      if ((int)it >= d) x += y;
+    }
+    s_beg[it] = a;
+    s_end[it] = b;
+    s_c0[it + 1] = x;
+    if (it == 0) s_c0[0] = 0u;
+  }
+  __syncthreads();
+}
+
+// the sub-bucket of chunk j (j below the chunk total): the last it with s_c0[it] <= j
+__device__ __forceinline__ uint32_t heavy_chunk_owner(const uint32_t* s_c0, uint32_t j) {
+  uint32_t lo = 0, n = kHeavyPar;
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {  // kHeavyPar = 2^6 candidates
+    const uint32_t half = n >> 1;
+    if (s_c0[lo + half] <= j) lo += half;
+    n -= half;
+  }
+  return lo;
+}
+
+// Calls f(it, a, b) for each chunk [a, b) of this workgroup, it its sub-bucket's place
+// in the list.  f is called by all threads and may use barriers.
+template <typename Fn>
+__device__ __forceinline__ void heavy_chunks(const uint32_t* sbb, const uint32_t* ov_list, uint32_t npar, Fn f) {
+  __shared__ uint32_t s_beg[kHeavyPar], s_end[kHeavyPar], s_c0[kHeavyPar + 1];
+  heavy_chunk_table(sbb, ov_list, npar, s_beg, s_end, s_c0);
+  const uint32_t nch = s_c0[kHeavyPar];
+  for (uint32_t j = blockIdx.x; j < nch; j += gridDim.x) {
+    const uint32_t it = heavy_chunk_owner(s_c0, j);
+    const uint32_t a = s_beg[it] + (j - s_c0[it]) * kSplitChunk;
+    const uint32_t b = s_end[it] - a > kSplitChunk ? a + kSplitChunk : s_end[it];
+    f(it, a, b);
+  }
+}
+
+// A wave's keys of one LDS counter combined (heavy_hot) into count[x(k)].
+template <typename X>
+__device__ __forceinline__ void heavy_count(const uint32_t* key, uint32_t a, uint32_t b, uint32_t* count, X x) {
+  const int lane = threadIdx.x & 63;
+  heavy_stream<false, uint32_t>(key, nullptr, a, b, [&](uint32_t k, uint32_t, bool ok) {
+    const uint32_t d = ok ? x(k) : 0u;
+    uint32_t hot;
+    const uint64_t m = heavy_hot(d, ok, hot);
+    if (ok && !((m >> lane) & 1ull)) atomicAdd(&count[d], 1u);
+    if (lane == 0 && m) atomicAdd(&count[hot], (uint32_t)__popcll(m));
+  });
+}
+
+// pairs of each row of the listed sub-buckets
+__global__ __launch_bounds__(kHeavyThreads) void k_heavy_rows(const uint32_t* __restrict__ ikey,
+                                                              const uint32_t* __restrict__ sbb, int colbits,
+                                                              const uint32_t* __restrict__ ov_list,
+                                                              const uint32_t* __restrict__ ov_count,
+                                                              uint32_t* __restrict__ hvy) {
+  __shared__ uint32_t s_rows[kHvyRows];
+  const uint32_t n_over = *ov_count;
+  const uint32_t npar = n_over < (uint32_t)kHeavyPar ? n_over : (uint32_t)kHeavyPar;
+  if (npar == 0) return;
+  heavy_chunks(sbb, ov_list, npar, [&](uint32_t it, uint32_t a, uint32_t b) {
+    for (int r = threadIdx.x; r < kHvyRows; r += kHeavyThreads) s_rows[r] = 0u;
+    __syncthreads();
+    heavy_count(ikey, a, b, s_rows, [&](uint32_t k) { return k >> colbits; });
+    __syncthreads();
+    const HeavyTable t(hvy, it);
+    for (int r = threadIdx.x; r < kHvyRows; r += kHeavyThreads) {
+      const uint32_t c = s_rows[r];
+      if (c) atomicAdd(&t.rpair[r], c);
+    }
+    __syncthreads();
+  });
+}
+
+// one workgroup (kHvyRows threads) per listed sub-bucket: the digits of each row, the
+// digit counts cleared
+__global__ __launch_bounds__(kHvyRows) void k_heavy_layout(const uint32_t* __restrict__ sbb, int colbits,
+                                                           const uint32_t* __restrict__ ov_list,
+                                                           const uint32_t* __restrict__ ov_count,
+                                                           uint32_t* __restrict__ hvy) {
+  __shared__ uint32_t s_scan[kHvyRows / 64 + 1];
+  const uint32_t n_over = *ov_count;
+  const uint32_t it = blockIdx.x;
+  if (it >= n_over || it >= (uint32_t)kHeavyPar) return;
+  const HeavyTable t(hvy, it);
+  const uint32_t g = ov_list[it];
+  const uint64_t n = sbb[g + 1] - sbb[g];
+  const int r = threadIdx.x;
+  const uint32_t c = t.rpair[r];
+  const int lg_max = colbits > 12 ? colbits - 12 : 0;  // digits no narrower than a leaf
+  const int lg_min = colbits > 23 ? colbits - 23 : 0;  // nor wider than 2^23 keys
+  int lg = 0;
+  if (c) {
+    const uint64_t q = (uint64_t)c * kHvyShare / n;
+    lg = q > 1 ? 63 - __clzll((long long)q) : 0;
+    lg = lg < lg_min ? lg_min : (lg > lg_max ? lg_max : lg);
+  }
+  const uint32_t nr = c ? 1u << lg : 0u;
+  uint32_t total;
+  const uint32_t base = block_scan_u32(nr, s_scan, &total);
+  t.rbase[r] = base;
+  t.rsh[r] = (uint32_t)(colbits - lg);
+  if (r == 0) {
+    t.rbase[kHvyRows] = total;
+    t.meta[0] = total;
+  }
+  for (uint32_t d = threadIdx.x; d < total; d += kHvyRows) {
+    t.hist[d] = 0u;
+    t.ucnt[d] = 0u;
+  }
+}
+
+// a sub-bucket's digit layout into LDS (s_rbase: kHvyRows + 1 words, s_rsh: kHvyRows)
+__device__ __forceinline__ void heavy_load_layout(const HeavyTable& t, uint32_t* s_rbase, uint32_t* s_rsh) {
+  for (int r = threadIdx.x; r <= kHvyRows; r += blockDim.x) {
+    s_rbase[r] = t.rbase[r];
+    if (r < kHvyRows) s_rsh[r] = t.rsh[r];
+  }
+}
+
+// pairs per first-level digit, summed over the chunks into the table's hist
+__global__ __launch_bounds__(kHeavyThreads) void k_heavy_hist(const uint32_t* __restrict__ ikey,
+                                                              const uint32_t* __restrict__ sbb, int colbits,
+                                                              const uint32_t* __restrict__ ov_list,
+                                                              const uint32_t* __restrict__ ov_count,
+                                                              uint32_t* __restrict__ hvy) {
+  __shared__ uint32_t s_hist[kHvyDigits];
+  __shared__ uint32_t s_rbase[kHvyRows + 1], s_rsh[kHvyRows];
+  const uint32_t n_over = *ov_count;
+  const uint32_t npar = n_over < (uint32_t)kHeavyPar ? n_over : (uint32_t)kHeavyPar;
+  if (npar == 0) return;
+  heavy_chunks(sbb, ov_list, npar, [&](uint32_t it, uint32_t a, uint32_t b) {
+    const HeavyTable t(hvy, it);
+    heavy_load_layout(t, s_rbase, s_rsh);
+    for (int d = threadIdx.x; d < kHvyDigits; d += kHeavyThreads) s_hist[d] = 0u;
+    __syncthreads();
+    const uint32_t nd = s_rbase[kHvyRows];
+    heavy_count(ikey, a, b, s_hist, [&](uint32_t k) { return heavy_digit(k, colbits, s_rbase, s_rsh); });
+    __syncthreads();
+    for (uint32_t d = threadIdx.x; d < nd; d += kHeavyThreads) {
+      const uint32_t c = s_hist[d];
+      if (c) atomicAdd(&t.hist[d], c);
+    }
+    __syncthreads();
+  });
+}
+
+// one workgroup per listed sub-bucket: the digit starts (absolute pair positions) from
+// the digit counts, which become the scatter's cursors
+__global__ __launch_bounds__(kHeavyThreads) void k_heavy_starts(const uint32_t* __restrict__ sbb,
+                                                                const uint32_t* __restrict__ ov_list,
+                                                                const uint32_t* __restrict__ ov_count,
+                                                                uint32_t* __restrict__ hvy) {
+  __shared__ uint32_t s_off[kHvyDigits];
+  __shared__ uint32_t s_scan[kHeavyThreads / 64 + 1];
+  const uint32_t n_over = *ov_count;
+  const uint32_t it = blockIdx.x;
+  if (it >= n_over || it >= (uint32_t)kHeavyPar) return;
+  const HeavyTable t(hvy, it);
+  const uint32_t nd = t.meta[0];
+  const uint32_t g = ov_list[it];
+  const uint32_t beg = sbb[g], end = sbb[g + 1];
+  for (uint32_t d = threadIdx.x; d < nd; d += kHeavyThreads) s_off[d] = t.hist[d];
+  __syncthreads();
+  block_scan_array(s_off, (int)nd, s_scan);  // (ends with a barrier)
+  for (uint32_t d = threadIdx.x; d < nd; d += kHeavyThreads) {
+    t.st[d] = beg + s_off[d];
+    t.hist[d] = beg + s_off[d];
+  }
+  if (threadIdx.x == 0) t.st[nd] = end;
+}
+
+// each chunk's pairs moved from (ikey, ival) to (akey, aval) in first-level digit order:
+// the chunk's digit counts taken again, a block of each digit reserved from the table's
+// cursors, then each pair placed in its digit's block
+template <typename V>
+__global__ __launch_bounds__(kHeavyThreads) void k_heavy_scatter(const uint32_t* __restrict__ ikey,
+                                                                 const V* __restrict__ ival,
+                                                                 uint32_t* __restrict__ akey, V* __restrict__ aval,
+                                                                 const uint32_t* __restrict__ sbb, int colbits,
+                                                                 const uint32_t* __restrict__ ov_list,
+                                                                 const uint32_t* __restrict__ ov_count,
+                                                                 uint32_t* __restrict__ hvy) {
+  __shared__ uint32_t s_hist[kHvyDigits];
+  __shared__ uint32_t s_rbase[kHvyRows + 1], s_rsh[kHvyRows];
+  const uint32_t n_over = *ov_count;
+  const uint32_t npar = n_over < (uint32_t)kHeavyPar ? n_over : (uint32_t)kHeavyPar;
+  if (npar == 0) return;
+  const int lane = threadIdx.x & 63;
+  heavy_chunks(sbb, ov_list, npar, [&](uint32_t it, uint32_t a, uint32_t b) {
+    const HeavyTable t(hvy, it);
+    heavy_load_layout(t, s_rbase, s_rsh);
+    for (int d = threadIdx.x; d < kHvyDigits; d += kHeavyThreads) s_hist[d] = 0u;
+    __syncthreads();
+    const uint32_t nd = s_rbase[kHvyRows];
+    heavy_count(ikey, a, b, s_hist, [&](uint32_t k) { return heavy_digit(k, colbits, s_rbase, s_rsh); });
+    __syncthreads();
+    for (uint32_t d = threadIdx.x; d < nd; d += kHeavyThreads) {
+      const uint32_t c = s_hist[d];
+      s_hist[d] = c ? atomicAdd(&t.hist[d], c) : 0u;
+    }
+    __syncthreads();
+    heavy_stream<true, V>(ikey, ival, a, b, [&](uint32_t k, V v, bool ok) {
+      const uint32_t d = ok ? heavy_digit(k, colbits, s_rbase, s_rsh) : 0u;
+      uint32_t hot;
+      const uint64_t m = heavy_hot(d, ok, hot);
+      uint32_t base = 0;
+      if (lane == 0 && m) base = atomicAdd(&s_hist[hot], (uint32_t)__popcll(m));
+      base = __shfl(base, 0, 64);
+      const bool mine = (m >> lane) & 1ull;
+      uint32_t pos = 0;
+      if (mine)
+        pos = base + (uint32_t)__popcll(m & ((1ull << lane) - 1));
+      else if (ok)
+        pos = atomicAdd(&s_hist[d], 1u);
+      if (ok) {
+        akey[pos] = k;
+        aval[pos] = v;
+      }
+    });
+    __syncthreads();
+  });
+}
+
+// The first-level digit ranges of the first kHeavyPar listed sub-buckets, split by
+// k_heavy_scatter: range d0 of sub-bucket it is reduced by workgroup d0 mod gridDim.x,
+// its entries written from its own first pair's place (its pairs all read before;
+// other workgroups read other ranges), its entry count recorded in the table and added
+// to its row's.
 template <typename V, bool RES = false>
 __global__ __launch_bounds__(kHeavyThreads) void k_pass3_heavy_ranges(uint32_t* ikey, V* ival, uint32_t* akey,
                                                                     V* aval, int colbits,
@@ -1657,36 +1943,58 @@ __global__ __launch_bounds__(kHeavyThreads) void k_pass3_heavy_ranges(uint32_t* 
   __syncthreads();
   const int F = 1117 - (int)*emax;
   int32_t* const tcol = (int32_t*)akey;
+  // the layout of the sub-bucket in hand, in the first of the two split-start arrays
+  // (heavy_range uses the second)
+  uint32_t* const s_rbase = sm.start;
+  uint32_t* const s_rsh = sm.start + kHvyRows + 1;
+  static_assert(2 * kHvyRows + 1 <= kDigits + 1, "the row layout fits one split-start array");
   for (uint32_t it = 0; it < npar; ++it) {
     const HeavyTable t(hvy, it);
-    const uint32_t nd0 = t.meta[2];
-    if (nd0 == 0) continue;  // reduced whole by k_pass3_heavy
-    const uint32_t kmin = t.meta[0], sh0 = t.meta[1], w0 = t.meta[3];
+    heavy_load_layout(t, s_rbase, s_rsh);
+    __syncthreads();
+    const uint32_t nd0 = s_rbase[kHvyRows];
     for (uint32_t d0 = blockIdx.x; d0 < nd0; d0 += gridDim.x) {
       const uint32_t a = t.st[d0], b = t.st[d0 + 1];
       if (a == b) continue;
-      const uint32_t k0 = kmin + (d0 << sh0);
-      const uint32_t w1 = (1u << sh0) < (kmin + w0 - k0) ? (1u << sh0) : (kmin + w0 - k0);
-      const uint32_t U = heavy_range<V, RES>(sm, ikey, ival, akey, aval, a, b, k0, w1, F, colbits, tcol + a,
-                                             aval + a, RES ? tres + a : nullptr, 0);
-      if (threadIdx.x == 0) t.ucnt[d0] = U;
-      for (int r = threadIdx.x; r < 256; r += kHeavyThreads) {
-        const uint32_t c = sm.rowcnt[r];
-        if (c) {
-          atomicAdd(&t.rcnt[r], c);
-          sm.rowcnt[r] = 0u;
-        }
+      uint32_t r = 0, n = kHvyRows;  // the row of digit d0: the last r with s_rbase[r] <= d0
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {  // kHvyRows = 2^8 candidates
+        const uint32_t half = n >> 1;
+        if (s_rbase[r + half] <= d0) r += half;
+        n -= half;
       }
-      heavy_sync();
+      const uint32_t sh = s_rsh[r];
+      const uint32_t k0 = (r << colbits) + ((d0 - s_rbase[r]) << sh);
+      const uint32_t U = heavy_range<V, RES>(sm, ikey, ival, akey, aval, a, b, k0, 1u << sh, F, colbits, tcol + a,
+                                             aval + a, RES ? tres + a : nullptr, 0);
+      if (threadIdx.x == 0) {
+        t.ucnt[d0] = U;
+        atomicAdd(&t.rcnt[r], U);
+      }
     }
+    __syncthreads();  // (the next layout overwrites this one)
   }
 }
 
-// One workgroup per sub-bucket of the table: the ranges' entries moved together, in
-// range order, to the sub-bucket's first pair's place (as k_pass3_heavy leaves them), the
-// row offsets within the sub-bucket and its entry count.  A range's entries move down
-// (never past the next range's first pair): each chunk is read, parked in LDS, and only
-// then written.
+// last index d in [0, n) with off[d] <= f (off nondecreasing, off[0] <= f)
+template <typename P>
+__device__ __forceinline__ uint32_t heavy_find(P off, uint32_t n, uint32_t f) {
+  uint32_t lo = 0;
+  while (n > 1) {
+    const uint32_t half = n >> 1;
+    if (off[lo + half] <= f) lo += half;
+    n -= half;
+  }
+  return lo;
+}
+
+constexpr uint32_t kFinalWave = 4096;  // entries one wavefront of k_final copies
+
+// One workgroup per sub-bucket of the table: its ranges' entry counts replaced by their
+// offsets (k_final_heavy gathers the entries from the ranges through them), the row
+// offsets within the sub-bucket and its entry count.  A sub-bucket of at most
+// kFinalWave entries, which k_final copies as one run from its first pair's place, has
+// them moved there: each thread reads its entries, and writes them after a barrier.
 constexpr int kFinishThreads = 1024;
 template <typename V, bool RES = false>
 __global__ __launch_bounds__(kFinishThreads) void k_pass3_heavy_finish(uint32_t* akey, V* aval, V* tres,
@@ -1695,44 +2003,43 @@ __global__ __launch_bounds__(kFinishThreads) void k_pass3_heavy_finish(uint32_t*
                                                                      uint32_t* __restrict__ usub,
                                                                      const uint32_t* __restrict__ ov_list,
                                                                      const uint32_t* __restrict__ ov_count,
-                                                                     const uint32_t* __restrict__ hvy) {
-  __shared__ uint32_t s_off[kDigits + 1];
+                                                                     uint32_t* __restrict__ hvy) {
+  __shared__ uint32_t s_off[kHvyDigits];
   __shared__ uint32_t s_scan[kFinishThreads / 64 + 1];
-  __shared__ int32_t s_col[kFinishThreads];
-  __shared__ V s_val[kFinishThreads];
-  __shared__ V s_res[RES ? kFinishThreads : 1];
   const uint32_t n_over = *ov_count;
   const uint32_t it = blockIdx.x;
   if (it >= n_over || it >= (uint32_t)kHeavyPar) return;
-  const HeavyTable t(const_cast<uint32_t*>(hvy), it);
-  const uint32_t nd0 = t.meta[2];
-  if (nd0 == 0) return;
+  const HeavyTable t(hvy, it);
+  const uint32_t nd0 = t.meta[0];
   const int64_t g = ov_list[it];
   const uint32_t beg = sbb[g];
   for (uint32_t d = threadIdx.x; d < nd0; d += kFinishThreads) s_off[d] = t.ucnt[d];
   __syncthreads();
   const uint32_t U = block_scan_array(s_off, (int)nd0, s_scan);  // (ends with a barrier)
-  if (threadIdx.x == 0) s_off[nd0] = U;
-  __syncthreads();
+  for (uint32_t d = threadIdx.x; d < nd0; d += kFinishThreads) t.ucnt[d] = s_off[d];
   int32_t* const tcol = (int32_t*)akey;
-  for (uint32_t d = 0; d < nd0; ++d) {
-    const uint32_t n = s_off[d + 1] - s_off[d];
-    const uint32_t src = t.st[d], dst = beg + s_off[d];
-    if (n == 0 || src == dst) continue;
-    for (uint32_t c = 0; c < n; c += kFinishThreads) {
-      const uint32_t f = c + threadIdx.x;
-      if (f < n) {
-        s_col[threadIdx.x] = tcol[src + f];
-        s_val[threadIdx.x] = aval[src + f];
-        if constexpr (RES) s_res[threadIdx.x] = tres[src + f];
-      }
-      __syncthreads();
-      if (f < n) {
-        tcol[dst + f] = s_col[threadIdx.x];
-        aval[dst + f] = s_val[threadIdx.x];
-        if constexpr (RES) tres[dst + f] = s_res[threadIdx.x];
-      }
-      __syncthreads();
+  if (U <= kFinalWave) {
+    constexpr int PER = kFinalWave / kFinishThreads;
+    int32_t c[PER];
+    V v[PER], e[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const uint32_t f = j * kFinishThreads + threadIdx.x;
+      if (f >= U) continue;
+      const uint32_t d = heavy_find(s_off, nd0, f);
+      const uint32_t src = t.st[d] + (f - s_off[d]);
+      c[j] = tcol[src];
+      v[j] = aval[src];
+      if constexpr (RES) e[j] = tres[src];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const uint32_t f = j * kFinishThreads + threadIdx.x;
+      if (f >= U) continue;
+      tcol[beg + f] = c[j];
+      aval[beg + f] = v[j];
+      if constexpr (RES) tres[beg + f] = e[j];
     }
   }
   // row offsets within the sub-bucket from the entries per row
@@ -1765,7 +2072,6 @@ __global__ __launch_bounds__(kFinishThreads) void k_pass3_heavy_finish(uint32_t*
 }
 
 // ------------------------------------------------------------------------- final
-constexpr uint32_t kFinalWave = 4096;  // entries one wavefront of k_final copies
 // One wavefront per sub-bucket g: its entries copied to their final place ubase[g],
 // its rows' row_ptr = ubase[g] + local row offset.
 // GROUPED (running sums of a grouped build): also each entry's residual (tres -> res)
@@ -1807,8 +2113,11 @@ __global__ __launch_bounds__(256) void k_final(const uint32_t* __restrict__ sbb,
 
 // The entries of the sub-buckets k_final leaves (more than kFinalWave: only a heavy
 // sub-bucket, listed by pass 3, can hold more than a pass-3 table), copied by all the
-// workgroups of the grid in chunks of 1024; with GROUPED each entry's row is found by a
-// binary search of the sub-bucket's row offsets.
+// workgroups of the grid in chunks of 1024: from the sub-bucket's first pair's place
+// on, or, for the first kHeavyPar listed, from the digit ranges that hold them (entry f
+// of the range d whose entry offset is the last at or below f, at the range's start
+// plus f minus that offset).  With GROUPED each entry's row is found by a binary search
+// of the sub-bucket's row offsets.
 template <typename V, bool GROUPED = false>
 __global__ __launch_bounds__(256) void k_final_heavy(const uint32_t* __restrict__ sbb, const uint32_t* __restrict__ ubase,
                                                      const int32_t* __restrict__ tcol, const V* __restrict__ tval,
@@ -1816,15 +2125,25 @@ __global__ __launch_bounds__(256) void k_final_heavy(const uint32_t* __restrict_
                                                      int s2, int64_t n_node, int64_t nsub,
                                                      const uint32_t* __restrict__ ov_list,
                                                      const uint32_t* __restrict__ ov_count,
+                                                     const uint32_t* __restrict__ hvy,
                                                      int32_t* __restrict__ col_idx, V* __restrict__ vals,
                                                      V* __restrict__ res, int32_t* __restrict__ rows, int64_t cap) {
+  __shared__ uint32_t s_off[kHvyDigits];  // entry offsets of the ranges
   const uint32_t n_over = *ov_count;
   if (n_over == 0 || (int64_t)ubase[nsub] > cap) return;
   for (uint32_t it = 0; it < n_over; ++it) {
     const int64_t g = ov_list[it];
     const uint32_t base = ubase[g], U = ubase[g + 1] - base;
     if (U <= kFinalWave) continue;
-    const uint32_t src = sbb[g];
+    const uint32_t beg = sbb[g];
+    const bool ranged = it < (uint32_t)kHeavyPar;
+    const HeavyTable t(const_cast<uint32_t*>(hvy), ranged ? it : 0u);
+    const uint32_t nd0 = ranged ? t.meta[0] : 0u;
+    if (ranged) {
+      __syncthreads();  // (the previous sub-bucket's offsets are no longer read)
+      for (uint32_t d = threadIdx.x; d < nd0; d += blockDim.x) s_off[d] = t.ucnt[d];
+      __syncthreads();
+    }
     const int64_t r0 = g << s2;
     const int R = (int)min((int64_t)1 << s2, n_node - r0);
     for (uint32_t c = blockIdx.x * 1024u; c < U; c += gridDim.x * 1024u) {
@@ -1832,10 +2151,15 @@ __global__ __launch_bounds__(256) void k_final_heavy(const uint32_t* __restrict_
       for (int j = 0; j < 4; ++j) {
         const uint32_t f = c + j * 256 + threadIdx.x;
         if (f >= U) continue;
-        col_idx[base + f] = tcol[src + f];
-        vals[base + f] = tval[src + f];
+        uint32_t src = beg + f;
+        if (ranged) {
+          const uint32_t d = heavy_find(s_off, nd0, f);
+          src = t.st[d] + (f - s_off[d]);
+        }
+        col_idx[base + f] = tcol[src];
+        vals[base + f] = tval[src];
         if constexpr (GROUPED) {
-          res[base + f] = tres[src + f];
+          res[base + f] = tres[src];
           int lo = 0, hi = R - 1;  // last row whose first entry is at or before f
           while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;

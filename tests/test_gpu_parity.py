@@ -270,6 +270,40 @@ def test_heavy_row(n_tets, center_last, prec):
     assert err <= TOL[prec]
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32fb64"])
+def test_many_heavy_rows(prec):
+    """Ninety-six stars of 3000 tets, each centre numbered last within its star: 96 rows
+    of 9001 entries, each in a sub-bucket of its own and past every table, so that as
+    many sub-buckets are listed for the heavy path as the many-workgroup split takes
+    (64) and more go to the single-workgroup one.  Every entry against the oracle, and
+    the same matrix bit for bit on a second build (the list order differs from run to
+    run)."""
+    k, n = 96, 3000
+    fans = [_fan(n, True, seed=s) for s in range(k)]
+    nn = fans[0].n_node
+    conn = np.concatenate([f.conn + i * nn for i, f in enumerate(fans)]).astype(np.int32)
+    X = np.concatenate([f.coords + 10.0 * i for i, f in enumerate(fans)])
+    m = meshgen.Mesh(4, conn, X, np.concatenate([f.coef for f in fans]))
+    say(f"[many-heavy] {k} stars of {n} tets {prec}")
+    r = gpu_build(m, prec)
+    rp, col, val = np_csr(r)
+    again = np_csr(gpu_build(m, prec))
+    for x, y in zip((rp, col, val), again):
+        assert np.array_equal(x.view(np.uint8), y.view(np.uint8))
+    orp, ocol, oval, _ = oracle.build_mesh(m)
+    np.testing.assert_array_equal(rp, orp)
+    np.testing.assert_array_equal(col, ocol)
+    # each centre's diagonal against the correctly rounded sum of its elements' values
+    klow, _ = oracle.integrate_lower(m.elem, m.conn, m.coords, m.coef)
+    oval = oval.copy()
+    for i in range(k):
+        c = (i + 1) * nn - 1
+        oval[orp[c + 1] - 1] = math.fsum(klow[i * n:(i + 1) * n, 0].tolist())
+    err = scaled_error(orp, ocol, val, oval)
+    say(f"  nnz={len(col):,} scaled error {err:.2e}")
+    assert err <= TOL[prec]
+
+
 def test_capacity_flag():
     m = meshgen.config_mesh(1)
     r = gpu_build(m, "fp64", cap=1000, check=False)
