@@ -24,6 +24,13 @@ permutation, coefficient, loss weights, spare):
   positively oriented in the undistorted grid.
 * Optional uniformly random node relabelling and element reordering.
 * Coefficient: constant, or log-uniform ``exp(U[ln lo, ln hi])``.
+
+A fan (``fan_mesh``) is n tets around one shared node: tet t is (centre, 1+3t, 2+3t,
+3+3t) with its three corners at ``s * R (I + E)`` rows, E i.i.d. U[-0.2, 0.2] (so
+``||E|| < 1`` and I + E keeps the positive orientation of the unit corner tet), s
+U[0.5, 2] and R a proper rotation from a normalised Gaussian quaternion; coefficient
+``exp(U[-2, 2])``.  With ``center_last`` the centre takes the largest id (the others
+shift down by one), so that its row holds every element's pairs.
 """
 from __future__ import annotations
 
@@ -233,6 +240,32 @@ def element_matrices(n_elem: int, nd: int, seed: int = 6) -> np.ndarray:
     """Seeded N(0,1) packed lower triangles [n_elem, nd(nd+1)/2] of symmetric element
     matrices (inputs of the assembly-only paths; no physics)."""
     return streams(seed)[5].standard_normal((n_elem, nd * (nd + 1) // 2))
+
+
+def fan_mesh(n_tets: int, center_last: bool = True, seed: int = 0) -> Mesh:
+    """n_tets tets sharing one node (recipe in the module docstring): a node of valence
+    n_tets, whose row (centre last) or column (centre first) collects every element."""
+    rng = np.random.default_rng(seed)
+    nn = 1 + 3 * n_tets
+    q = rng.standard_normal((n_tets, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    w, x, y, z = q.T
+    R = np.stack([np.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)], -1),
+                  np.stack([2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)], -1),
+                  np.stack([2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)], -1)], 1)
+    corner = np.eye(3)[None] + rng.uniform(-0.2, 0.2, (n_tets, 3, 3))  # rows: the three corners
+    scale = rng.uniform(0.5, 2.0, (n_tets, 1, 1))
+    X = np.zeros((nn, 3))
+    X[1:] = (scale * corner @ np.transpose(R, (0, 2, 1))).reshape(-1, 3)
+    t = np.arange(n_tets)
+    conn = np.stack([np.zeros(n_tets, np.int64), 1 + 3 * t, 2 + 3 * t, 3 + 3 * t], axis=1)
+    if center_last:
+        perm = np.roll(np.arange(nn), 1)  # old 0 -> nn-1, old i -> i-1
+        newX = np.empty_like(X)
+        newX[perm] = X
+        conn = perm[conn]
+        X = newX
+    return Mesh(4, conn.astype(np.int32), X, np.exp(rng.uniform(-2, 2, n_tets)))
 
 
 def box_nnz(elem: int, nx: int, ny: int, nz: int) -> int:

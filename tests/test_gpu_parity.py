@@ -210,34 +210,19 @@ def test_unused_nodes_have_empty_rows():
 
 
 def _fan(n_tets, center_last, seed=0):
-    """n_tets tets sharing one node: its row (or diagonal) collects every element.  Each
-    tet is the corner tet (0, e1, e2, e3), jittered by 0.2, scaled by 0.5..2 and turned
-    by a random rotation: shapes stay well conditioned, so FP64 integration error stays
-    near rounding (randomly placed corners make nearly flat tets whose values carry
-    relative errors of 1e-11 in any FP64 evaluation)."""
-    rng = np.random.default_rng(seed)
-    nn = 1 + 3 * n_tets
-    Q, Rq = np.linalg.qr(rng.standard_normal((n_tets, 3, 3)))
-    Q = Q * np.sign(np.diagonal(Rq, axis1=1, axis2=2))[:, None, :]
-    Q[np.linalg.det(Q) < 0, :, 0] *= -1.0  # proper rotations
-    corner = np.eye(3)[None] + 0.2 * rng.standard_normal((n_tets, 3, 3))  # rows: the three corners
-    scale = rng.uniform(0.5, 2.0, (n_tets, 1, 1))
-    X = np.zeros((nn, 3))
-    X[1:] = (scale * corner @ np.transpose(Q, (0, 2, 1))).reshape(-1, 3)
-    t = np.arange(n_tets)
-    conn = np.stack([np.zeros(n_tets, np.int64), 1 + 3 * t, 2 + 3 * t, 3 + 3 * t], axis=1)
-    # orientation: det [1 x_a]_(a=0..3) with x_0 = 0 is det [x_1; x_2; x_3]
-    neg = np.linalg.det(X[conn[:, 1:]]) < 0
-    conn[neg, 2], conn[neg, 3] = conn[neg, 3].copy(), conn[neg, 2].copy()
-    conn = conn.astype(np.int32)
-    if center_last:
-        # relabel: centre gets the largest id, so its row holds 4 entries per element
-        perm = np.roll(np.arange(nn), 1)  # old 0 -> nn-1, old i -> i-1
-        newX = np.empty_like(X)
-        newX[perm] = X
-        conn = perm[conn].astype(np.int32)
-        X = newX
-    return meshgen.Mesh(4, conn, X, np.exp(rng.uniform(-2, 2, n_tets)))
+    """n_tets well-shaped tets sharing one node (meshgen.fan_mesh): its row (centre last)
+    or diagonal collects every element."""
+    return meshgen.fan_mesh(n_tets, center_last, seed)
+
+
+def _stars(k, n):
+    """k fans of n tets side by side (node ids in blocks of 3 n + 1, each centre last in
+    its block; coordinates shifted apart)."""
+    fans = [_fan(n, True, seed=s) for s in range(k)]
+    nn = fans[0].n_node
+    conn = np.concatenate([f.conn + i * nn for i, f in enumerate(fans)]).astype(np.int32)
+    X = np.concatenate([f.coords + 10.0 * i for i, f in enumerate(fans)])
+    return meshgen.Mesh(4, conn, X, np.concatenate([f.coef for f in fans]))
 
 
 @pytest.mark.parametrize("n_tets,center_last", [(5000, False), (5000, True), (20000, True), (200000, True),
@@ -279,11 +264,8 @@ def test_many_heavy_rows(prec):
     the same matrix bit for bit on a second build (the list order differs from run to
     run)."""
     k, n = 96, 3000
-    fans = [_fan(n, True, seed=s) for s in range(k)]
-    nn = fans[0].n_node
-    conn = np.concatenate([f.conn + i * nn for i, f in enumerate(fans)]).astype(np.int32)
-    X = np.concatenate([f.coords + 10.0 * i for i, f in enumerate(fans)])
-    m = meshgen.Mesh(4, conn, X, np.concatenate([f.coef for f in fans]))
+    m = _stars(k, n)
+    nn = m.n_node // k
     say(f"[many-heavy] {k} stars of {n} tets {prec}")
     r = gpu_build(m, prec)
     rp, col, val = np_csr(r)

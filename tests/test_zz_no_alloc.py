@@ -66,6 +66,25 @@ def test_noalloc_matches_workspace_build_twice(elem, prec):
         assert err <= TOL[prec]
 
 
+def test_noalloc_heavy_rows_twice():
+    """Meshes whose rows overflow every table, through the fixed scratch: 80 stars of 2000
+    tets (more heavy sub-buckets than the many-workgroup split takes), then one star of
+    20,000 tets (a row of 60,001 entries); both bit for bit the workspace build's."""
+    from tests.test_gpu_parity import _fan, _stars
+
+    for name, m in (("80 stars of 2000", _stars(80, 2000)), ("star of 20000", _fan(20000, True, seed=3))):
+        for prec in ("fp32fb64", "fp64"):
+            ws_bytes, _ = kb.plan(m.elem, m.n_elem, m.n_node, prec)
+            assert ws_bytes <= _lib.KB_SCRATCH_BYTES
+            say(f"[noalloc-heavy] {name} {prec} workspace {ws_bytes / 2**20:.1f} MiB")
+            rp, col, val, _ = _noalloc(m, prec)
+            ref = kb.build_lower_csr(*to_dev(m), m.elem, prec=prec)
+            rrp, rcol, rval = (t.cpu().numpy() for t in (ref.row_ptr, ref.col_idx, ref.vals))
+            np.testing.assert_array_equal(rp, rrp)
+            np.testing.assert_array_equal(col, rcol)
+            assert np.array_equal(val.view(np.uint8), rval.view(np.uint8))
+
+
 def test_noalloc_refuses_a_mesh_beyond_the_scratch():
     m = meshgen.config_mesh(3, n=60)  # 1.3M tets: its workspace is larger than the scratch
     ws_bytes, _ = kb.plan(m.elem, m.n_elem, m.n_node, "fp32fb64")
