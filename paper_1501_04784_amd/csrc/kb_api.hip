@@ -252,7 +252,7 @@ int make_plan(const kb_mesh* m, int prec, const kb_tuning* tu, Plan* p, int dof 
   p->o_seg2b = take(4 * (size_t)p->nseg_max);
   p->o_emax = take(8);  // largest value exponent, then the count of heavy sub-buckets
   p->o_ovl = take(4 * (size_t)p->nsub);  // heavy sub-buckets (k_pass3_heavy)
-  p->o_hvy = take(4 * (size_t)kHeavyPar * kHvyWords);  // their first-level ranges (k_pass3_heavy_ranges)
+  p->o_hvy = take(4 * ((size_t)kHeavyPar * kHvyWords + kBigWords));  // their split tables and big leaves
   p->o_dconn = take(p->dof > 1 ? 4 * (size_t)p->nen * (size_t)p->nel : 0);  // expanded connectivity
   p->o_tres = take(csr_cap > 0 ? p->vbytes * T : 0);  // residuals of the reduced entries
   p->o_row1 = take(2 * T);
@@ -449,9 +449,9 @@ int launch_pass3(const Plan& p, uint32_t* key2, V* val2, uint32_t* sbb, uint32_t
   kh<<<gh, kHeavyThreads, HeavySmem::bytes(), s>>>(key2, val2, (uint32_t*)tcol, tval, sbb, p.s2, p.colbits, p.nn, emax,
                                                    tres, rowoff, usub, ov_list, ov_count, hvy);
   KB_LAUNCH_CHECK();
-  // up to kHeavyPar of them split by many workgroups, their first-level ranges reduced
-  // by one workgroup per compute unit, then their entries moved together (all return at
-  // once when there are none)
+  // up to kHeavyPar of them split by many workgroups, their big leaves summed by many
+  // workgroups, their first-level ranges reduced by one workgroup per compute unit, then
+  // their entry counts scanned (all return at once when there are none)
   const unsigned gsplit = (unsigned)std::max(1, 2 * p.cus);
   k_heavy_rows<<<gsplit, kHeavyThreads, 0, s>>>(key2, sbb, p.colbits, ov_list, ov_count, hvy);
   KB_LAUNCH_CHECK();
@@ -459,10 +459,15 @@ int launch_pass3(const Plan& p, uint32_t* key2, V* val2, uint32_t* sbb, uint32_t
   KB_LAUNCH_CHECK();
   k_heavy_hist<<<gsplit, kHeavyThreads, 0, s>>>(key2, sbb, p.colbits, ov_list, ov_count, hvy);
   KB_LAUNCH_CHECK();
-  k_heavy_starts<<<(unsigned)kHeavyPar, kHeavyThreads, 0, s>>>(sbb, ov_list, ov_count, hvy);
+  k_heavy_starts<<<(unsigned)kHeavyPar, kHeavyThreads, 0, s>>>(sbb, p.colbits, ov_list, ov_count, hvy);
   KB_LAUNCH_CHECK();
   k_heavy_scatter<V><<<gsplit, kHeavyThreads, 0, s>>>(key2, val2, (uint32_t*)tcol, tval, sbb, p.colbits, ov_list,
                                                       ov_count, hvy);
+  KB_LAUNCH_CHECK();
+  auto kl = k_heavy_bigleaf<V>;
+  if (!set_lds(kl, HeavySmem::bytes())) return KB_EHIP;
+  kl<<<(unsigned)std::max(1, p.cus), kHeavyThreads, HeavySmem::bytes(), s>>>((uint32_t*)tcol, tval, emax, ov_count,
+                                                                           hvy);
   KB_LAUNCH_CHECK();
   auto kr = k_pass3_heavy_ranges<V, RES>;
   if (!set_lds(kr, HeavySmem::bytes())) return KB_EHIP;

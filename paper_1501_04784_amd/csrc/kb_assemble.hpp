@@ -1449,14 +1449,15 @@ __device__ __forceinline__ void heavy_normalise(const HeavySmem& sm) {
   }
 }
 
-// sums of the leaf's pairs [a, b) (keys in [kmin, kmin + kLeafKeys)), appended in key
-// order at tcol / tval [u0 ...); returns the number of entries
-template <typename V, bool RES>
-__device__ uint32_t heavy_leaf(const HeavySmem& sm, const uint32_t* key, const V* val, uint32_t a, uint32_t b,
-                               uint32_t kmin, int F, int colbits, int32_t* tcol, V* tval, V* tres, uint32_t u0) {
-  // pairs per round: the carried sums (below 2^48) plus kRound chunks (below 2^48
-  // unsigned, below 2^47 in magnitude signed) stay inside 64 bits
-  constexpr uint32_t kRound = 65532;
+// pairs per round of a leaf: the carried sums (below 2^48) plus kRound chunks (below
+// 2^48 unsigned, below 2^47 in magnitude signed) stay inside 64 bits
+constexpr uint32_t kRound = 65532;
+
+// the exact sums of the leaf's pairs [a, b) (keys in [kmin, kmin + kLeafKeys)) into the
+// LDS slots, carried after every round (lo, hi below 2^48; occ set)
+template <typename V>
+__device__ void heavy_leaf_sum(const HeavySmem& sm, const uint32_t* key, const V* val, uint32_t a, uint32_t b,
+                               uint32_t kmin, int F) {
   const int lane = threadIdx.x & 63;
   // the wave's kept slot: once a slot has been hot (held by more than one lane), the
   // lanes that meet it again while it is the wave's first lane's slot add its chunks to
@@ -1511,6 +1512,14 @@ __device__ uint32_t heavy_leaf(const HeavySmem& sm, const uint32_t* key, const V
     heavy_normalise(sm);
     __syncthreads();
   }
+}
+
+// the occupied LDS slots (carried sums) as entries, appended in key order at tcol /
+// tval [u0 ...), the slots cleared; returns the number of entries
+template <typename V, bool RES>
+__device__ uint32_t heavy_leaf_emit(const HeavySmem& sm, uint32_t kmin, int F, int colbits, int32_t* tcol, V* tval,
+                                    V* tres, uint32_t u0) {
+  const int lane = threadIdx.x & 63;
   // the occupied slots in order: kLeafKeys / kHeavyThreads consecutive slots per lane
   constexpr int PL = kLeafKeys / kHeavyThreads;
   const int h0 = threadIdx.x * PL;
@@ -1550,6 +1559,43 @@ __device__ uint32_t heavy_leaf(const HeavySmem& sm, const uint32_t* key, const V
   heavy_sync();
   return total;
 }
+
+// sums of the leaf's pairs [a, b) (keys in [kmin, kmin + kLeafKeys)), appended in key
+// order at tcol / tval [u0 ...); returns the number of entries
+template <typename V, bool RES>
+__device__ uint32_t heavy_leaf(const HeavySmem& sm, const uint32_t* key, const V* val, uint32_t a, uint32_t b,
+                               uint32_t kmin, int F, int colbits, int32_t* tcol, V* tval, V* tres, uint32_t u0) {
+  heavy_leaf_sum<V>(sm, key, val, a, b, kmin, F);
+  return heavy_leaf_emit<V, RES>(sm, kmin, F, colbits, tcol, tval, tres, u0);
+}
+
+// Leaves of the split sub-buckets (first-level digit ranges no wider than a leaf) with
+// more than kBigLeafPairs pairs, such as the one holding a heavy node's diagonal, are
+// summed by several workgroups: k_heavy_starts lists up to kBigLeaves of them, each
+// workgroup of k_heavy_bigleaf sums one round (kRound pairs) of one of them into its LDS
+// slots and adds the carried sums (lo, hi below 2^48, top) of its occupied slots into
+// the leaf's accumulator with 64-bit atomics (exact: a leaf of fewer than 2^31 pairs has
+// fewer than 2^16 rounds), and k_pass3_heavy_ranges carries the accumulated sums once
+// more and writes the leaf's entries.  Leaves beyond the list are summed as the others.
+constexpr int kBigLeaves = 16;
+constexpr uint32_t kBigLeafPairs = 2 * kRound;
+constexpr int kBigRec = 8;  // words per listed leaf: it, d0, a, b, k0
+constexpr int kBigListWords = 8 + kBigRec * kBigLeaves;
+constexpr int kBigAccWords = 7 * kLeafKeys;  // lo, hi, top (64-bit) and occ (32-bit) per slot
+constexpr size_t kBigWords = kBigListWords + (size_t)kBigLeaves * kBigAccWords;
+struct BigLeaves {
+  uint32_t* list;  // [0] leaves listed (may exceed kBigLeaves), then the records
+  __device__ explicit BigLeaves(uint32_t* hvy) : list(hvy + (size_t)kHeavyPar * kHvyWords) {}
+  __device__ uint32_t count() const { return list[0] < (uint32_t)kBigLeaves ? list[0] : (uint32_t)kBigLeaves; }
+  __device__ uint32_t* rec(uint32_t i) const { return list + 8 + kBigRec * i; }
+  __device__ unsigned long long* lo(uint32_t i) const {
+    return (unsigned long long*)(list + kBigListWords + (size_t)i * kBigAccWords);
+  }
+  __device__ unsigned long long* hi(uint32_t i) const { return lo(i) + kLeafKeys; }
+  __device__ unsigned long long* top(uint32_t i) const { return lo(i) + 2 * kLeafKeys; }
+  __device__ uint32_t* occ(uint32_t i) const { return (uint32_t*)(lo(i) + 3 * kLeafKeys); }
+};
+static_assert(((size_t)kHeavyPar * kHvyWords + kBigListWords) % 2 == 0, "the accumulators are 8-byte aligned");
 
 // split width for a key range of w keys: 0 for a leaf, else the digit shift
 __device__ __forceinline__ int heavy_shift(uint32_t w) {
@@ -1596,6 +1642,7 @@ __global__ __launch_bounds__(kHeavyThreads) void k_pass3_heavy(uint32_t* ikey, V
   const uint32_t n_over = *ov_count;
   // (launched with at least kHeavyPar workgroups)
   if (blockIdx.x < n_over && blockIdx.x < (uint32_t)kHeavyPar) heavy_table_init(hvy, blockIdx.x);
+  if (blockIdx.x == 0 && threadIdx.x == 0 && n_over) BigLeaves(hvy).list[0] = 0u;
   if ((uint32_t)kHeavyPar + blockIdx.x >= n_over) return;
   for (int h = threadIdx.x; h < kLeafKeys; h += kHeavyThreads) {
     sm.lo[h] = 0ull;
@@ -1840,8 +1887,9 @@ __global__ __launch_bounds__(kHeavyThreads) void k_heavy_hist(const uint32_t* __
 }
 
 // one workgroup per listed sub-bucket: the digit starts (absolute pair positions) from
-// the digit counts, which become the scatter's cursors
-__global__ __launch_bounds__(kHeavyThreads) void k_heavy_starts(const uint32_t* __restrict__ sbb,
+// the digit counts, which become the scatter's cursors; digit ranges no wider than a
+// leaf with more than kBigLeafPairs pairs are listed as big leaves
+__global__ __launch_bounds__(kHeavyThreads) void k_heavy_starts(const uint32_t* __restrict__ sbb, int colbits,
                                                                 const uint32_t* __restrict__ ov_list,
                                                                 const uint32_t* __restrict__ ov_count,
                                                                 uint32_t* __restrict__ hvy) {
@@ -1857,9 +1905,32 @@ __global__ __launch_bounds__(kHeavyThreads) void k_heavy_starts(const uint32_t* 
   for (uint32_t d = threadIdx.x; d < nd; d += kHeavyThreads) s_off[d] = t.hist[d];
   __syncthreads();
   block_scan_array(s_off, (int)nd, s_scan);  // (ends with a barrier)
+  const BigLeaves big(hvy);
   for (uint32_t d = threadIdx.x; d < nd; d += kHeavyThreads) {
-    t.st[d] = beg + s_off[d];
-    t.hist[d] = beg + s_off[d];
+    const uint32_t a = beg + s_off[d], b = d + 1 < nd ? beg + s_off[d + 1] : end;
+    t.st[d] = a;
+    t.hist[d] = a;
+    if (b - a > kBigLeafPairs) {
+      // the row of digit d: the last r with rbase[r] <= d (rare: read from the table)
+      uint32_t r = 0, n = kHvyRows;
+      for (int s = 0; s < 8; ++s) {
+        const uint32_t half = n >> 1;
+        if (t.rbase[r + half] <= d) r += half;
+        n -= half;
+      }
+      const uint32_t sh = t.rsh[r];
+      if ((1u << sh) <= (uint32_t)kLeafKeys) {
+        const uint32_t i = atomicAdd(big.list, 1u);
+        if (i < (uint32_t)kBigLeaves) {
+          uint32_t* const q = big.rec(i);
+          q[0] = it;
+          q[1] = d;
+          q[2] = a;
+          q[3] = b;
+          q[4] = (r << colbits) + ((d - t.rbase[r]) << sh);
+        }
+      }
+    }
   }
   if (threadIdx.x == 0) t.st[nd] = end;
 }
@@ -1881,6 +1952,13 @@ __global__ __launch_bounds__(kHeavyThreads) void k_heavy_scatter(const uint32_t*
   const uint32_t npar = n_over < (uint32_t)kHeavyPar ? n_over : (uint32_t)kHeavyPar;
   if (npar == 0) return;
   const int lane = threadIdx.x & 63;
+  {  // the big leaves' accumulators cleared (k_heavy_bigleaf adds into them next)
+    const BigLeaves big(hvy);
+    uint32_t* const acc = big.list + kBigListWords;
+    const size_t nw = (size_t)big.count() * kBigAccWords;
+    for (size_t w = (size_t)blockIdx.x * kHeavyThreads + threadIdx.x; w < nw; w += (size_t)gridDim.x * kHeavyThreads)
+      acc[w] = 0u;
+  }
   heavy_chunks(sbb, ov_list, npar, [&](uint32_t it, uint32_t a, uint32_t b) {
     const HeavyTable t(hvy, it);
     heavy_load_layout(t, s_rbase, s_rsh);
@@ -1916,6 +1994,63 @@ __global__ __launch_bounds__(kHeavyThreads) void k_heavy_scatter(const uint32_t*
   });
 }
 
+// the rounds of the listed big leaves, one per workgroup at a time, added into their
+// accumulators (each leaf's pairs in (akey, aval) [a, b), keys from k0)
+template <typename V>
+__global__ __launch_bounds__(kHeavyThreads) void k_heavy_bigleaf(const uint32_t* akey, const V* aval,
+                                                                 const uint32_t* __restrict__ emax,
+                                                                 const uint32_t* __restrict__ ov_count,
+                                                                 uint32_t* __restrict__ hvy) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const HeavySmem sm(smem);
+  __shared__ uint32_t s_p0[kBigLeaves + 1];
+  if (*ov_count == 0) return;
+  const BigLeaves big(hvy);
+  const uint32_t nbig = big.count();
+  if (nbig == 0) return;
+  if (threadIdx.x == 0) {
+    uint32_t s = 0;
+    for (uint32_t i = 0; i < nbig; ++i) {
+      s_p0[i] = s;
+      s += (big.rec(i)[3] - big.rec(i)[2] + kRound - 1) / kRound;
+    }
+    s_p0[nbig] = s;
+  }
+  for (int h = threadIdx.x; h < kLeafKeys; h += kHeavyThreads) {
+    sm.lo[h] = 0ull;
+    sm.hi[h] = 0ll;
+    sm.top[h] = 0ll;
+  }
+  if (threadIdx.x < kLeafKeys / 4) ((uint32_t*)sm.occ)[threadIdx.x] = 0u;
+  __syncthreads();
+  const int F = 1117 - (int)*emax;
+  for (uint32_t p = blockIdx.x; p < s_p0[nbig]; p += gridDim.x) {
+    uint32_t i = 0;
+    while (i + 1 < nbig && s_p0[i + 1] <= p) ++i;
+    const uint32_t* const q = big.rec(i);
+    const uint32_t a = q[2] + (p - s_p0[i]) * kRound;
+    const uint32_t b = q[3] - a > kRound ? a + kRound : q[3];
+    heavy_leaf_sum<V>(sm, akey, aval, a, b, q[4], F);
+    unsigned long long* const glo = big.lo(i);
+    unsigned long long* const ghi = big.hi(i);
+    unsigned long long* const gtop = big.top(i);
+    uint32_t* const gocc = big.occ(i);
+    for (int h = threadIdx.x; h < kLeafKeys; h += kHeavyThreads) {
+      if (!sm.occ[h]) continue;
+      atomicAdd(&glo[h], sm.lo[h]);
+      atomicAdd(&ghi[h], (unsigned long long)sm.hi[h]);
+      atomicAdd(&gtop[h], (unsigned long long)sm.top[h]);
+      gocc[h] = 1u;
+      sm.lo[h] = 0ull;
+      sm.hi[h] = 0ll;
+      sm.top[h] = 0ll;
+    }
+    __syncthreads();
+    if (threadIdx.x < kLeafKeys / 4) ((uint32_t*)sm.occ)[threadIdx.x] = 0u;
+    __syncthreads();
+  }
+}
+
 // The first-level digit ranges of the first kHeavyPar listed sub-buckets, split by
 // k_heavy_scatter: range d0 of sub-bucket it is reduced by workgroup d0 mod gridDim.x,
 // its entries written from its own first pair's place (its pairs all read before;
@@ -1948,6 +2083,14 @@ __global__ __launch_bounds__(kHeavyThreads) void k_pass3_heavy_ranges(uint32_t* 
   uint32_t* const s_rbase = sm.start;
   uint32_t* const s_rsh = sm.start + kHvyRows + 1;
   static_assert(2 * kHvyRows + 1 <= kDigits + 1, "the row layout fits one split-start array");
+  // the big leaves (summed by k_heavy_bigleaf): their sub-bucket and digit
+  __shared__ uint32_t s_big[2 * kBigLeaves];
+  const BigLeaves big(hvy);
+  const uint32_t nbig = big.count();
+  if (threadIdx.x < nbig) {
+    s_big[2 * threadIdx.x] = big.rec(threadIdx.x)[0];
+    s_big[2 * threadIdx.x + 1] = big.rec(threadIdx.x)[1];
+  }
   for (uint32_t it = 0; it < npar; ++it) {
     const HeavyTable t(hvy, it);
     heavy_load_layout(t, s_rbase, s_rsh);
@@ -1965,8 +2108,30 @@ __global__ __launch_bounds__(kHeavyThreads) void k_pass3_heavy_ranges(uint32_t* 
       }
       const uint32_t sh = s_rsh[r];
       const uint32_t k0 = (r << colbits) + ((d0 - s_rbase[r]) << sh);
-      const uint32_t U = heavy_range<V, RES>(sm, ikey, ival, akey, aval, a, b, k0, 1u << sh, F, colbits, tcol + a,
-                                             aval + a, RES ? tres + a : nullptr, 0);
+      uint32_t bi = nbig;
+      for (uint32_t i = 0; i < nbig; ++i)
+        if (s_big[2 * i] == it && s_big[2 * i + 1] == d0) bi = i;
+      uint32_t U;
+      if (bi < nbig) {  // summed already: its accumulated sums carried once more
+        const unsigned long long* const glo = big.lo(bi);
+        const unsigned long long* const ghi = big.hi(bi);
+        const unsigned long long* const gtop = big.top(bi);
+        const uint32_t* const gocc = big.occ(bi);
+        for (int h = threadIdx.x; h < kLeafKeys; h += kHeavyThreads) {
+          if (!gocc[h]) continue;
+          sm.lo[h] = glo[h];
+          sm.hi[h] = (long long)ghi[h];
+          sm.top[h] = (long long)gtop[h];
+          sm.occ[h] = 1;
+        }
+        __syncthreads();
+        heavy_normalise(sm);
+        __syncthreads();
+        U = heavy_leaf_emit<V, RES>(sm, k0, F, colbits, tcol + a, aval + a, RES ? tres + a : nullptr, 0);
+      } else {
+        U = heavy_range<V, RES>(sm, ikey, ival, akey, aval, a, b, k0, 1u << sh, F, colbits, tcol + a, aval + a,
+                                RES ? tres + a : nullptr, 0);
+      }
       if (threadIdx.x == 0) {
         t.ucnt[d0] = U;
         atomicAdd(&t.rcnt[r], U);

@@ -134,15 +134,23 @@ def test_grouped_beyond_one_pass():
     check_sampled_rows(m, r, "fp32fb64", n_sample=400)
 
 
-def test_grouped_heavy_row_takes_the_fallback_path():
+def test_grouped_heavy_row_takes_the_heavy_path():
     """A star of 20,000 tets around one node whose id is the largest: its row gathers
     80,000 pairs, more than a sub-bucket's table holds, so each pass sums it on the
-    reduce kernel's single-lane path, with residuals carried between the groups."""
-    from tests.test_gpu_parity import _fan
-
-    m = _fan(20000, center_last=True, seed=3)
+    heavy path, with residuals carried between the groups."""
+    m = meshgen.fan_mesh(20000, True, seed=3)
     compare_to_single(m, "fp64", 6000)
     compare_to_single(m, "fp32fb64", 6000)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32fb64"])
+def test_grouped_heavy_diagonal_across_workgroups(prec):
+    """A star of 300,000 tets in two groups: each pass's heavy row has a diagonal of
+    150,000 pairs (plus the carried sum in the second), more than one workgroup sums
+    alone, so its leaf is summed by several workgroups, with residuals."""
+    m = meshgen.fan_mesh(300000, True, seed=5)
+    say(f"[grouped-big-leaf] {prec}")
+    compare_to_single(m, prec, 150000)
 
 
 @pytest.mark.parametrize("prec", ["fp32fb64", "fp64"])

@@ -69,10 +69,11 @@ def test_noalloc_matches_workspace_build_twice(elem, prec):
 def test_noalloc_heavy_rows_twice():
     """Meshes whose rows overflow every table, through the fixed scratch: 80 stars of 2000
     tets (more heavy sub-buckets than the many-workgroup split takes), then one star of
-    20,000 tets (a row of 60,001 entries); both bit for bit the workspace build's."""
-    from tests.test_gpu_parity import _fan, _stars
+    150,000 tets (a row of 450,001 entries whose diagonal leaf is summed by several
+    workgroups); both bit for bit the workspace build's."""
+    from tests.test_gpu_parity import _stars
 
-    for name, m in (("80 stars of 2000", _stars(80, 2000)), ("star of 20000", _fan(20000, True, seed=3))):
+    for name, m in (("80 stars of 2000", _stars(80, 2000)), ("star of 150000", meshgen.fan_mesh(150000, True, 3))):
         for prec in ("fp32fb64", "fp64"):
             ws_bytes, _ = kb.plan(m.elem, m.n_elem, m.n_node, prec)
             assert ws_bytes <= _lib.KB_SCRATCH_BYTES
