@@ -286,6 +286,37 @@ def test_many_heavy_rows(prec):
     assert err <= TOL[prec]
 
 
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32fb64"])
+def test_one_element_repeated(prec):
+    """40,000 copies of one tet over four nodes, each with its own coefficient: ten
+    entries, 400,000 pairs in one sub-bucket (past 2^16: the heavy path, with a 2-bit
+    column space and one digit per row).  Row 3's 160,000 pairs are more than one
+    workgroup sums alone (a big leaf), row 2's 120,000 take two carry rounds.  The build
+    against the oracle (each entry referred to the correctly rounded sum of the oracle's
+    element values, math.fsum); then the oracle's FP64 element values assembled by the
+    library, which must give exactly those correctly rounded sums (no bit of these
+    values falls below the fixed-point scale)."""
+    n = 40000
+    rng = np.random.default_rng(11)
+    conn = np.tile(np.arange(4, dtype=np.int32), (n, 1))
+    X = np.array([[0.0, 0.0, 0.0], [1.0, 0.1, 0.0], [0.2, 1.1, 0.0], [0.1, 0.2, 0.9]])
+    m = meshgen.Mesh(4, conn, X, np.exp(rng.uniform(-2, 2, n)))
+    say(f"[repeated] {n} copies of one tet {prec}")
+    rp, col, val = np_csr(gpu_build(m, prec))
+    np.testing.assert_array_equal(rp, [0, 1, 3, 6, 10])
+    np.testing.assert_array_equal(col, [0, 0, 1, 0, 1, 2, 0, 1, 2, 3])
+    klow, _ = oracle.integrate_lower(m.elem, m.conn, m.coords, m.coef)
+    want = np.array([math.fsum(klow[:, t].tolist()) for t in range(10)])  # lower order = CSR order here
+    err = scaled_error(rp, col, val.astype(np.float64), want)
+    say(f"  scaled error {err:.2e}")
+    assert err <= TOL[prec]
+    if prec == "fp64":
+        d = torch.device("cuda:0")
+        r = kb.assemble_lower_csr(torch.from_numpy(conn).to(d), 4, torch.from_numpy(klow).to(d), 4, prec="fp64")
+        got = r.vals[:10].cpu().numpy()
+        assert np.array_equal(got.view(np.uint64), want.view(np.uint64)), (got - want) / np.spacing(want)
+
 def test_capacity_flag():
     m = meshgen.config_mesh(1)
     r = gpu_build(m, "fp64", cap=1000, check=False)
