@@ -1062,17 +1062,19 @@ __global__ __launch_bounds__(NT) void k_scatter2(const uint16_t* __restrict__ ir
 // with n_r about kHvyShare times the row's share of the pairs, at most one digit per
 // leaf width of columns, and at least 2^(colbits - 23) so that a digit is at most 2^23
 // keys wide (split once more into leaves).  A row holding most pairs of its sub-bucket
-// is thus cut into leaf-wide digits that many workgroups reduce side by side.  The
-// digits of all rows total at most kHvyShare + 256 + 256 = kHvyDigits.
+// thus gets 2048 digits, leaf-wide up to 2^23 columns, which many workgroups reduce
+// side by side.  The digits of all rows total at most kHvyShare + 256 + 256 =
+// kHvyDigits.
 constexpr int kHeavyPar = 64;
-constexpr int kHvyDigits = 2048;  // first-level digits at most (= kDigits of the heavy section)
-constexpr uint32_t kHvyShare = 1536;
+constexpr int kHvyDigits = 4096;  // first-level digits at most
+constexpr uint32_t kHvyShare = 3584;
 constexpr int kHvyRows = 256;  // rows of a sub-bucket at most
-constexpr int kHvyWords = (kHvyDigits + 1) + 2 * kHvyDigits + 3 * kHvyRows + (kHvyRows + 1) + 4;
+constexpr int kHvyWords = (kHvyDigits + 1) + kHvyDigits + 3 * kHvyRows + (kHvyRows + 1) + 4;
 struct HeavyTable {
   uint32_t* st;     // [kHvyDigits + 1] digit starts (absolute pair positions)
-  uint32_t* ucnt;   // [kHvyDigits] entries of each digit range, then their offsets
   uint32_t* hist;   // [kHvyDigits] pairs of each digit, then the scatter's cursors
+  uint32_t* ucnt;   // the same words once the scatter is done: the entries of each digit
+                    // range (every range writes its own), then their offsets
   uint32_t* rcnt;   // [kHvyRows] entries of each row
   uint32_t* rpair;  // [kHvyRows] pairs of each row
   uint32_t* rsh;    // [kHvyRows] column shift of each row's digits
@@ -1080,8 +1082,8 @@ struct HeavyTable {
   uint32_t* meta;   // [4] digits
   __device__ HeavyTable(uint32_t* hvy, uint32_t it) {
     st = hvy + (size_t)it * kHvyWords;
-    ucnt = st + kHvyDigits + 1;
-    hist = ucnt + kHvyDigits;
+    hist = st + kHvyDigits + 1;
+    ucnt = hist;
     rcnt = hist + kHvyDigits;
     rpair = rcnt + kHvyRows;
     rsh = rpair + kHvyRows;
@@ -1577,7 +1579,7 @@ __device__ uint32_t heavy_leaf(const HeavySmem& sm, const uint32_t* key, const V
 // the leaf's accumulator with 64-bit atomics (exact: a leaf of fewer than 2^31 pairs has
 // fewer than 2^16 rounds), and k_pass3_heavy_ranges carries the accumulated sums once
 // more and writes the leaf's entries.  Leaves beyond the list are summed as the others.
-constexpr int kBigLeaves = 16;
+constexpr int kBigLeaves = 8;
 constexpr uint32_t kBigLeafPairs = 2 * kRound;
 constexpr int kBigRec = 8;  // words per listed leaf: it, d0, a, b, k0
 constexpr int kBigListWords = 8 + kBigRec * kBigLeaves;
@@ -1845,10 +1847,7 @@ __global__ __launch_bounds__(kHvyRows) void k_heavy_layout(const uint32_t* __res
     t.rbase[kHvyRows] = total;
     t.meta[0] = total;
   }
-  for (uint32_t d = threadIdx.x; d < total; d += kHvyRows) {
-    t.hist[d] = 0u;
-    t.ucnt[d] = 0u;
-  }
+  for (uint32_t d = threadIdx.x; d < total; d += kHvyRows) t.hist[d] = 0u;
 }
 
 // a sub-bucket's digit layout into LDS (s_rbase: kHvyRows + 1 words, s_rsh: kHvyRows)
@@ -2098,7 +2097,10 @@ __global__ __launch_bounds__(kHeavyThreads) void k_pass3_heavy_ranges(uint32_t* 
     const uint32_t nd0 = s_rbase[kHvyRows];
     for (uint32_t d0 = blockIdx.x; d0 < nd0; d0 += gridDim.x) {
       const uint32_t a = t.st[d0], b = t.st[d0 + 1];
-      if (a == b) continue;
+      if (a == b) {  // (its count word still holds the scatter's cursor)
+        if (threadIdx.x == 0) t.ucnt[d0] = 0u;
+        continue;
+      }
       uint32_t r = 0, n = kHvyRows;  // the row of digit d0: the last r with s_rbase[r] <= d0
 #pragma unroll
       for (int s = 0; s < 8; ++s) {  // kHvyRows = 2^8 candidates
