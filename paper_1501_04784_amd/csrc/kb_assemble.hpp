@@ -1313,8 +1313,10 @@ __global__ __launch_bounds__(256) void k_pass3(uint32_t* __restrict__ ikey, V* _
 
 // ------------------------------------------------------------ heavy sub-buckets
 // A sub-bucket that overflows pass 3 (a node shared by very many elements: its row holds
-// more distinct entries than an LDS table, or more than 2^16 pairs) is reduced by one
-// 1024-lane workgroup, which splits it by key into ranges of at most kLeafKeys keys:
+// more distinct entries than an LDS table, or more than 2^16 pairs) is split by key into
+// ranges of at most kLeafKeys keys, each summed into a direct-addressed LDS table.  The
+// first kHeavyPar listed are split by the whole device (k_heavy_*, the tables above);
+// each further one is reduced whole by one 1024-lane workgroup of k_pass3_heavy:
 //   - the key range [kmin, kmax] of the sub-bucket; a range wider than kLeafKeys is split
 //     into at most 2048 digit ranges of 2^shift keys (a histogram, its scan and a
 //     scatter into the other buffer, at the same place), twice at most for 31-bit keys;
@@ -1629,6 +1631,8 @@ __device__ uint32_t heavy_range(const HeavySmem& sm, uint32_t* ikey, V* ival, ui
   return U;
 }
 
+// The listed sub-buckets after the first kHeavyPar, one workgroup each; its first
+// kHeavyPar workgroups also clear the first kHeavyPar tables and the big-leaf count
 // (the pair buffers alias the output, so they carry no __restrict__)
 template <typename V, bool RES = false>
 __global__ __launch_bounds__(kHeavyThreads) void k_pass3_heavy(uint32_t* ikey, V* ival, uint32_t* akey, V* aval,
