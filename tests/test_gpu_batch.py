@@ -112,6 +112,48 @@ def test_batch_graph_capture_replays():
         _ = torch.ones(1 << 20, device="cuda").sum().item()  # eager work between replays
 
 
+
+def test_batch_with_heavy_rows_and_graph_replay():
+    """A batch holding two fans among small tet boxes: a centre-last fan of 150,000 tets
+    (a row of 450,001 entries whose diagonal is summed by several workgroups) and a
+    centre-first one.  Each mesh's CSR has its own build's pattern and values to 1e-13 of
+    the largest (the batch sums at one common scale); the batched build captured in a
+    HIP graph replays to the eager result bit for bit, the heavy path included."""
+    meshes = [meshgen.box_mesh(4, 3, jitter=0.2, coef=(0.5, 2.0), seed=1), meshgen.fan_mesh(150000, True, seed=2),
+              meshgen.box_mesh(4, 4, 3, 2, jitter=0.2, seed=4), meshgen.fan_mesh(3000, False, seed=5)]
+    say(f"[batch-heavy] meshes={len(meshes)} nel={sum(m.n_elem for m in meshes)}")
+    batch = kb.pack_batch(as_tuples(meshes), 4)
+    b = kb.BatchBuilder(batch, prec="fp64")
+    b.run()
+    eager = [(r.row_ptr.clone(), r.col_idx.clone(), r.vals.clone()) for r in b.results()]
+    d = torch.device("cuda:0")
+    for m, (rp, col, val) in zip(meshes, eager):
+        one = kb.build_lower_csr(torch.from_numpy(m.conn).to(d), torch.from_numpy(m.coords).to(d),
+                                 torch.from_numpy(m.coef).to(d), 4, prec="fp64")
+        assert torch.equal(one.row_ptr, rp) and torch.equal(one.col_idx, col)
+        np.testing.assert_allclose(one.vals.cpu().numpy(), val.cpu().numpy(), rtol=0,
+                                   atol=1e-13 * float(one.vals.abs().max()))
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        b.run()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        b.run()
+    for rep in range(3):
+        b.col_idx.fill_(-7)
+        b.vals.fill_(float("nan"))
+        b.row_ptr.fill_(-7)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for (rp, col, val), r in zip(eager, b.results()):
+            assert torch.equal(rp, r.row_ptr) and torch.equal(col, r.col_idx)
+            assert torch.equal(val, r.vals), f"replay {rep}"
+        _ = torch.ones(1 << 20, device="cuda").sum().item()  # eager work between replays
+
 def test_batch_local_id_out_of_range_is_flagged():
     meshes = small_batch(4, 4, seed=5)
     bad = meshes[1]
