@@ -102,6 +102,23 @@ def test_dof_fp32_sums_are_exact_then_rounded_once(elem, dof):
     np.testing.assert_array_equal(val.view(np.uint32), want.view(np.uint32))
 
 
+@pytest.mark.parametrize("dof", [2, 3])
+def test_dof_heavy_rows_exact(dof):
+    """A fan of 6000 tets around one node numbered last, with dof components per node:
+    each of the centre's dof rows holds about 18,000 dof entries, more than a table (the
+    heavy path).  The pattern against the oracle, and every entry the exact sum of its
+    float32 contributions rounded once."""
+    m = meshgen.fan_mesh(6000, True, seed=8)
+    klow = values_for(m, dof, "fp32", 50 + dof)
+    say(f"[dof-heavy] dof={dof} nel={m.n_elem} nn={m.n_node}")
+    rp, col, val = host(gpu_assemble(m, dof, "fp32", klow))
+    orp, ocol, _, of = oracle.assemble_lower_csr_dof(4, dof, m.conn, m.n_node, klow.astype(np.float64))
+    assert of == 0
+    np.testing.assert_array_equal(rp, orp)
+    np.testing.assert_array_equal(col, ocol)
+    want = exact_sums_f32(4, dof, m.conn, klow)
+    np.testing.assert_array_equal(val.view(np.uint32), want.view(np.uint32))
+
 @pytest.mark.parametrize("tuning", [kb.Tuning(bucket_bits=3, sub_bits=1), kb.Tuning(block=128),
                                     kb.Tuning(bucket_bits=8, sub_bits=8)])
 @pytest.mark.parametrize("dof", [2, 3])
