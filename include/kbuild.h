@@ -169,6 +169,9 @@ int kb_plan(const kb_mesh* mesh, int prec, const kb_tuning* tuning, size_t* ws_b
  *   nnz_dev   device int64, receives nnz
  *   status_dev device uint32[KB_STATUS_WORDS], overwritten (see above)
  *   stream    hipStream_t (NULL = default stream)
+ * A node may be shared by any number of elements.  Rows whose entries or pairs
+ * overflow the reduction's local tables (a hub node's row) are reduced on a separate
+ * path that spreads them over the device, with the same exact sums and so the same bits.
  */
 int kb_build_lower_csr(const kb_mesh* mesh, int prec, const kb_tuning* tuning, void* ws, size_t ws_bytes,
                        int32_t* row_ptr, int32_t* col_idx, void* vals, int64_t cap, int64_t* nnz_dev,
